@@ -67,6 +67,10 @@ def _load():
         lib.orc_nbf_cart.restype = c_int
         lib.orc_sfac.argtypes = [POINTER(OrcSys), c_int, dp, dp, dp]
         lib.orc_sfac.restype = c_int
+        lib.orc_ctx_new.argtypes = [POINTER(OrcSys)]
+        lib.orc_ctx_new.restype = ctypes.c_void_p
+        lib.orc_ctx_free.argtypes = [ctypes.c_void_p]
+        lib.orc_ctx_sfac.argtypes = [ctypes.c_void_p, c_int, dp, dp, dp]
         lib.orc_overlap.argtypes = [POINTER(OrcSys), dp]
         lib.orc_overlap.restype = c_int
         lib.orc_pair_list.argtypes = [POINTER(OrcSys), c_long, ip, ip, ip, ip, ip, dp]
@@ -344,8 +348,17 @@ def jk(system, D=None, omega=None, thr=None, bra_shells: Optional[Sequence[int]]
     if "lr" in want:
         G, w = glist(system, omega, thr)
         nG = G.shape[0]
+        lib = _load()
+        ctx = lib.orc_ctx_new(ctypes.byref(s.c))
+        if not ctx:
+            raise ValueError("oracle rejected the basis")
+        fr = np.zeros((g_chunk, nbc, nbc))
+        fi = np.zeros((g_chunk, nbc, nbc))
         for g0 in range(0, nG, g_chunk):
-            F = structure_factors(system, G[g0:g0 + g_chunk], omega, thr)
+            Gc = np.ascontiguousarray(G[g0:g0 + g_chunk])
+            ng = Gc.shape[0]
+            lib.orc_ctx_sfac(ctx, ng, _dp(Gc), _dp(fr), _dp(fi))
+            F = fr[:ng] + 1j * fi[:ng]
             for k in range(F.shape[0]):
                 Fg = F[k]
                 wg = w[g0 + k]
@@ -356,6 +369,7 @@ def jk(system, D=None, omega=None, thr=None, bra_shells: Optional[Sequence[int]]
                 else:
                     Jlr[rows] += wg * np.real(np.conj(Fg[rows]) * rhoD)
                     Klr[rows] += wg * np.real(np.conj(Fg[rows]) @ Dc @ Fg.T)
+        lib.orc_ctx_free(ctx)
     Jself = np.zeros((nbc, nbc)); Kself = np.zeros((nbc, nbc))
     if "self" in want:
         S = overlap_cart(system, omega, thr)

@@ -431,6 +431,8 @@ typedef struct {
     double Q;                    /* Cauchy-Schwarz value of the local pair    */
     double *E;                   /* 3 axes of Hermite coefficients            */
     int n2[3];                   /* lattice index of the image offset         */
+    double Na[ORC_MAXNC], Nb[ORC_MAXNC];  /* component normalisations         */
+    double S0;                   /* c_a c_b (pi/p)^{3/2}                      */
 } pair_t;
 
 typedef struct {
@@ -488,6 +490,8 @@ static void pair_cb(const double R[3], const int n[3], void *u_)
     }
     u->n++;
 }
+
+static void comp_norms(int l, double a, double *N);
 
 static void ctx_free(ctx_t *X)
 {
@@ -572,6 +576,9 @@ static int ctx_build(const orc_sys *in, ctx_t *X)
         double Pc[3];
         P->E = X->Epool + eo;
         pair_E(P->la, P->lb, P->a, P->b, P->A, P->B, P->E, Pc);
+        comp_norms(P->la, P->a, P->Na);
+        comp_norms(P->lb, P->b, P->Nb);
+        P->S0 = P->ca * P->cb * pow(ORC_PI / P->p, 1.5);
         for (int x = 0; x < 3; ++x) P->P[x] = Pc[x];
         eo += 3 * (P->la + 1) * (P->lb + 1) * (P->la + P->lb + 1);
     }
@@ -850,11 +857,9 @@ int orc_nbf_cart(const orc_sys *in)
  *   = c_a c_b N N (pi/p)^{3/2} e^{-G^2/4p} e^{-iG.P} sum_t E_t (-iG)^t
  * (the reciprocal factor of Sec. 2.4, eq. pbc_eri_general_final, split into
  * bra and ket).  F_re/F_im: nG x nbfc x nbfc. */
-int orc_sfac(const orc_sys *in, int nG, const double *G, double *Fre, double *Fim)
+static void sfac_ctx(const ctx_t *X, int nG, const double *G, double *Fre, double *Fim)
 {
-    ctx_t X;
-    if (ctx_build(in, &X)) { ctx_free(&X); return -1; }
-    long nb = X.nbfc;
+    long nb = X->nbfc;
     memset(Fre, 0, sizeof(double) * nG * nb * nb);
     memset(Fim, 0, sizeof(double) * nG * nb * nb);
 #pragma omp parallel for schedule(dynamic, 1)
@@ -862,15 +867,14 @@ int orc_sfac(const orc_sys *in, int nG, const double *G, double *Fre, double *Fi
         const double *Gv = G + 3 * g;
         double G2 = Gv[0] * Gv[0] + Gv[1] * Gv[1] + Gv[2] * Gv[2];
         double *fr = Fre + (size_t)g * nb * nb, *fi = Fim + (size_t)g * nb * nb;
-        for (long ip = 0; ip < X.npair; ++ip) {
-            const pair_t *P = &X.pair[ip];
-            double Na[ORC_MAXNC], Nb[ORC_MAXNC];
-            comp_norms(P->la, P->a, Na); comp_norms(P->lb, P->b, Nb);
-            double pre = P->ca * P->cb * pow(ORC_PI / P->p, 1.5) * exp(-G2 / (4.0 * P->p));
+        for (long ip = 0; ip < X->npair; ++ip) {
+            const pair_t *P = &X->pair[ip];
+            const double *Na = P->Na, *Nb = P->Nb;
+            double pre = P->S0 * exp(-G2 / (4.0 * P->p));
             double ph = -(Gv[0] * P->P[0] + Gv[1] * P->P[1] + Gv[2] * P->P[2]);
             double complex phase = cexp(I * ph);
             int sz = (P->la + 1) * (P->lb + 1) * (P->la + P->lb + 1), nt = P->la + P->lb + 1;
-            long aoA = X.sh[P->sa].ao, aoB = X.sh[P->sb].ao;
+            long aoA = X->sh[P->sa].ao, aoB = X->sh[P->sb].ao;
             for (int i = 0; i < ncart(P->la); ++i) {
                 int ca[3]; cart_comp(P->la, i, ca);
                 for (int j = 0; j < ncart(P->lb); ++j) {
@@ -878,12 +882,12 @@ int orc_sfac(const orc_sys *in, int nG, const double *G, double *Fre, double *Fi
                     double complex h[3];
                     for (int x = 0; x < 3; ++x) {
                         const double *e = P->E + x * sz + (ca[x] * (P->lb + 1) + cb[x]) * nt;
-                        double complex s = 0, f = 1;
+                        double complex sm = 0, f = 1;
                         for (int t = 0; t <= ca[x] + cb[x]; ++t) {
-                            s += e[t] * f;
+                            sm += e[t] * f;
                             f *= -I * Gv[x];
                         }
-                        h[x] = s;
+                        h[x] = sm;
                     }
                     double complex v = pre * Na[i] * Nb[j] * h[0] * h[1] * h[2] * phase;
                     fr[(aoA + i) * nb + aoB + j] += creal(v);
@@ -892,8 +896,39 @@ int orc_sfac(const orc_sys *in, int nG, const double *G, double *Fre, double *Fi
             }
         }
     }
+}
+
+/* Pair structure factors rho_{mu nu}(G) = sum over local pairs of
+ *   int e^{-iG.r} mu(r) nu(r - R2) dr
+ *   = c_a c_b N N (pi/p)^{3/2} e^{-G^2/4p} e^{-iG.P} sum_t E_t (-iG)^t
+ * (the reciprocal factor of Sec. 2.4, eq. pbc_eri_general_final, split into
+ * bra and ket).  F_re/F_im: nG x nbfc x nbfc. */
+int orc_sfac(const orc_sys *in, int nG, const double *G, double *Fre, double *Fim)
+{
+    ctx_t X;
+    if (ctx_build(in, &X)) { ctx_free(&X); return -1; }
+    sfac_ctx(&X, nG, G, Fre, Fim);
     ctx_free(&X);
     return 0;
+}
+
+/* The same with a context kept between calls (pair list built once). */
+void *orc_ctx_new(const orc_sys *in)
+{
+    ctx_t *X = (ctx_t *)malloc(sizeof(ctx_t));
+    if (!X) return NULL;
+    if (ctx_build(in, X)) { ctx_free(X); free(X); return NULL; }
+    return X;
+}
+void orc_ctx_free(void *X)
+{
+    if (!X) return;
+    ctx_free((ctx_t *)X);
+    free(X);
+}
+void orc_ctx_sfac(void *X, int nG, const double *G, double *Fre, double *Fim)
+{
+    sfac_ctx((const ctx_t *)X, nG, G, Fre, Fim);
 }
 
 /* Gamma overlap over the local pair list (Sec. 2.2, eq. pbc_overlap_formula). */

@@ -1,0 +1,446 @@
+// C ABI of the periodic J/K library (see include/pbcjk.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "pbcjk.h"
+
+using namespace pbcjk;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                            \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess) return fail(PBC_JK_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+template <class T>
+int dalloc(T **p, size_t n)
+{
+    *p = nullptr;
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc((void **)p, n * sizeof(T));
+    if (e != hipSuccess) return fail(PBC_JK_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    return 0;
+}
+
+template <class T>
+int upload(T **p, const std::vector<T> &v)
+{
+    int rc = dalloc(p, v.size());
+    if (rc) return rc;
+    if (!v.empty()) HIPCHK(hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return 0;
+}
+
+}  // namespace
+
+struct pbc_jk {
+    Setup S;
+    int device = 0;
+    int parts = PBC_JK_PART_SR | PBC_JK_PART_LR | PBC_JK_PART_SELF;
+    hipStream_t own = nullptr;
+    // setup data
+    PairRec *d_pairs = nullptr;
+    GroupRec *d_groups = nullptr;
+    double *d_boys = nullptr, *d_S = nullptr, *d_G = nullptr, *d_Gw = nullptr;
+    int *d_sp_start = nullptr, *d_sp_pairs = nullptr, *d_sp_shA = nullptr, *d_sp_shB = nullptr;
+    int *d_sh_l = nullptr, *d_sh_aoc = nullptr, *d_tr_ao = nullptr, *d_inv_ci = nullptr;
+    double *d_tr_c = nullptr, *d_dscale = nullptr, *d_inv_cc = nullptr;
+    // build work space
+    double *d_D = nullptr, *d_Dt = nullptr, *d_Dmax = nullptr, *d_X = nullptr, *d_Y = nullptr;
+    double *d_Jt = nullptr, *d_Kt = nullptr, *d_F = nullptr, *d_T = nullptr, *d_rho = nullptr;
+    double *d_scal = nullptr, *d_Jo = nullptr, *d_Ko = nullptr;
+    unsigned long long *d_dmaxg = nullptr, *d_cnt = nullptr;
+    int gchunk = 0;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool timed = false;
+    pbc_jk_counters st{};
+};
+
+namespace {
+
+void release(pbc_jk *h)
+{
+    void *ptrs[] = {h->d_pairs, h->d_groups, h->d_boys, h->d_S, h->d_G, h->d_Gw, h->d_sp_start, h->d_sp_pairs,
+                    h->d_sp_shA, h->d_sp_shB, h->d_sh_l, h->d_sh_aoc, h->d_tr_ao, h->d_inv_ci, h->d_tr_c,
+                    h->d_dscale, h->d_inv_cc, h->d_D, h->d_Dt, h->d_Dmax, h->d_X, h->d_Y, h->d_Jt, h->d_Kt,
+                    h->d_F, h->d_T, h->d_rho, h->d_scal, h->d_Jo, h->d_Ko, h->d_dmaxg, h->d_cnt};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    for (auto &e : h->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (h->own) (void)hipStreamDestroy(h->own);
+}
+
+int create_device(pbc_jk *h)
+{
+    Setup &S = h->S;
+    HIPCHK(hipGetDevice(&h->device));
+    HIPCHK(hipStreamCreateWithFlags(&h->own, hipStreamNonBlocking));
+    for (auto &e : h->ev) HIPCHK(hipEventCreate(&e));
+    int rc;
+    if ((rc = upload(&h->d_pairs, S.pairs))) return rc;
+    if ((rc = upload(&h->d_groups, S.groups))) return rc;
+    if ((rc = upload(&h->d_boys, S.boys))) return rc;
+    if ((rc = upload(&h->d_S, S.S))) return rc;
+    if ((rc = upload(&h->d_G, S.G))) return rc;
+    if ((rc = upload(&h->d_Gw, S.Gw))) return rc;
+    if ((rc = upload(&h->d_sp_start, S.sp_start))) return rc;
+    if ((rc = upload(&h->d_sp_pairs, S.sp_pairs))) return rc;
+    if ((rc = upload(&h->d_sp_shA, S.sp_shA))) return rc;
+    if ((rc = upload(&h->d_sp_shB, S.sp_shB))) return rc;
+    if ((rc = upload(&h->d_sh_l, S.sh_l))) return rc;
+    if ((rc = upload(&h->d_sh_aoc, S.sh_aoc))) return rc;
+    if ((rc = upload(&h->d_tr_ao, S.tr_ao))) return rc;
+    if ((rc = upload(&h->d_tr_c, S.tr_c))) return rc;
+    if ((rc = upload(&h->d_dscale, S.dscale))) return rc;
+    // inverse transform: output AO -> up to three (Cartesian index, coefficient)
+    std::vector<int> ici(3 * S.nbf, -1);
+    std::vector<double> icc(3 * S.nbf, 0.0);
+    std::vector<int> fillc(S.nbf, 0);
+    for (int i = 0; i < S.nbfc; ++i)
+        for (int u = 0; u < 2; ++u) {
+            int a = S.tr_ao[2 * i + u];
+            if (a < 0) continue;
+            int k = fillc[a]++;
+            if (k >= 3) return fail(PBC_JK_EINVAL, "internal: transform fan-in above 3");
+            ici[3 * a + k] = i;
+            icc[3 * a + k] = S.tr_c[2 * i + u];
+        }
+    if ((rc = upload(&h->d_inv_ci, ici))) return rc;
+    if ((rc = upload(&h->d_inv_cc, icc))) return rc;
+
+    const size_t n2 = (size_t)S.nbfc * S.nbfc, m2 = (size_t)S.nbf * S.nbf;
+    if ((rc = dalloc(&h->d_D, m2))) return rc;
+    if ((rc = dalloc(&h->d_Dt, n2))) return rc;
+    if ((rc = dalloc(&h->d_Dmax, (size_t)S.nshell * S.nshell))) return rc;
+    if ((rc = dalloc(&h->d_X, n2))) return rc;
+    if ((rc = dalloc(&h->d_Y, n2))) return rc;
+    if ((rc = dalloc(&h->d_Jt, n2))) return rc;
+    if ((rc = dalloc(&h->d_Kt, n2))) return rc;
+    if ((rc = dalloc(&h->d_Jo, m2))) return rc;
+    if ((rc = dalloc(&h->d_Ko, m2))) return rc;
+    if ((rc = dalloc(&h->d_scal, 4))) return rc;
+    if ((rc = dalloc(&h->d_dmaxg, 1))) return rc;
+    if ((rc = dalloc(&h->d_cnt, 4))) return rc;
+    // reciprocal-space chunk: F and T hold 2 * gchunk matrices each
+    const int nG = (int)S.Gw.size();
+    double budget_mb = 16384.0;
+    if (const char *e = std::getenv("PBCJK_LR_BUDGET_MB")) budget_mb = std::max(64.0, std::atof(e));
+    long per = (long)(budget_mb * 1048576.0 / (4.0 * 8.0 * (double)n2));
+    h->gchunk = (int)std::max(1L, std::min<long>(per, std::max(nG, 1)));
+    if ((rc = dalloc(&h->d_F, 2 * (size_t)h->gchunk * n2))) return rc;
+    if ((rc = dalloc(&h->d_T, std::max<size_t>(2 * (size_t)h->gchunk * n2, n2)))) return rc;
+    if ((rc = dalloc(&h->d_rho, 2 * (size_t)h->gchunk))) return rc;
+    return 0;
+}
+
+int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, double *E_K, hipStream_t st)
+{
+    Setup &S = h->S;
+    const int n = S.nbfc, nb = S.nbf;
+    const long n2 = (long)n * n, m2 = (long)nb * nb;
+    const bool wantJ = dJ || E_J, wantK = dK || E_K;
+    double *Jo = dJ ? dJ : h->d_Jo;
+    double *Ko = dK ? dK : h->d_Ko;
+    HIPCHK(hipEventRecord(h->ev[0], st));
+
+    // B1: density in the scaled Cartesian basis, block maxima
+    HIPCHK(launch_fill((double *)h->d_dmaxg, 1, 0.0, st));
+    DprepArgs dp{dD, nb, n, S.nshell, h->d_tr_ao, h->d_tr_c, h->d_dscale, h->d_sh_aoc, h->d_sh_l,
+                 h->d_Dt, h->d_Dmax, h->d_dmaxg};
+    HIPCHK(launch_dprep(dp, st));
+    HIPCHK(launch_fill(h->d_X, n2, 0.0, st));
+    HIPCHK(launch_fill(h->d_Y, n2, 0.0, st));
+    HIPCHK(launch_fill(h->d_Jt, n2, 0.0, st));
+    HIPCHK(launch_fill(h->d_Kt, n2, 0.0, st));
+    HIPCHK(launch_fill((double *)h->d_cnt, 4, 0.0, st));
+
+    // B3/B4: short-range J and K
+    if (h->parts & PBC_JK_PART_SR) {
+        SRArgs a{};
+        a.pairs = h->d_pairs; a.groups = h->d_groups;
+        a.Dt = h->d_Dt; a.Dmax = h->d_Dmax; a.dmax_glob = (const double *)h->d_dmaxg;
+        a.X = h->d_X; a.Y = h->d_Y; a.nbfc = n; a.nshell = S.nshell;
+        std::memcpy(a.M, S.lat.M, sizeof a.M);
+        std::memcpy(a.Minv, S.lat.Minv, sizeof a.Minv);
+        std::memcpy(a.span, S.lat.span, sizeof a.span);
+        a.w2 = S.omega * S.omega; a.d_schwarz = S.d_schwarz; a.d_ewald_R = S.d_ewald_R;
+        a.rcap2 = S.r_cut > 0 ? S.r_cut * S.r_cut : 0.0;
+        a.boys = h->d_boys; a.counters = h->d_cnt;
+        for (int cb = 0; cb < kNumClass; ++cb)
+            for (int ck = cb; ck < kNumClass; ++ck) {
+                a.gb0 = S.class_start[cb]; a.nb = S.class_start[cb + 1] - S.class_start[cb];
+                a.gk0 = S.class_start[ck]; a.nk = S.class_start[ck + 1] - S.class_start[ck];
+                a.tri = (cb == ck);
+                if (a.nb == 0 || a.nk == 0) continue;
+                hipError_t e = launch_sr_jk(cb, ck, a, st);
+                if (e == hipErrorNotSupported) return fail(PBC_JK_ENOTSUP, "d-shell kernels not built");
+                HIPCHK(e);
+            }
+    }
+    HIPCHK(hipEventRecord(h->ev[1], st));
+
+    // B5/B6: reciprocal-space J and K
+    const int nG = (int)S.Gw.size();
+    if ((h->parts & PBC_JK_PART_LR) && nG > 0 && (wantJ || wantK)) {
+        SfacArgs sa{};
+        sa.pairs = h->d_pairs; sa.sp_start = h->d_sp_start; sa.sp_pairs = h->d_sp_pairs;
+        sa.sp_shA = h->d_sp_shA; sa.sp_shB = h->d_sp_shB; sa.sh_l = h->d_sh_l; sa.sh_aoc = h->d_sh_aoc;
+        sa.nsp = (int)S.sp_shA.size(); sa.F = h->d_F; sa.nbfc = n;
+        for (int g0 = 0; g0 < nG; g0 += h->gchunk) {
+            const int gc = std::min(h->gchunk, nG - g0);
+            HIPCHK(launch_fill(h->d_F, 2L * gc * n2, 0.0, st));
+            sa.G = h->d_G + 3 * g0; sa.ng = gc;
+            HIPCHK(launch_sfac(sa, st));
+            if (wantJ) {
+                HIPCHK(launch_dot_batched(h->d_F, h->d_Dt, (int)n2, 2 * gc, h->d_rho, st));
+                HIPCHK(launch_jlr(h->d_F, h->d_rho, h->d_Gw + g0, gc, (int)n2, h->d_Jt, st));
+            }
+            if (wantK) {
+                GemmArgs g1{};
+                g1.M = g1.N = g1.K = n;
+                g1.A = h->d_F; g1.lda = n; g1.sA = n2;
+                g1.B = h->d_Dt; g1.ldb = n; g1.sB = 0;
+                g1.C = h->d_T; g1.ldc = n; g1.sC = n2;
+                g1.nbatch = 2 * gc; g1.alpha = nullptr; g1.alpha0 = 1.0; g1.reduce = 0; g1.slices = 1;
+                HIPCHK(launch_dgemm(g1, st));
+                // K_LR += sum_b W_b T_b F_b; weights repeat for the real and imaginary halves
+                for (int half = 0; half < 2; ++half) {
+                    GemmArgs g2{};
+                    g2.M = g2.N = g2.K = n;
+                    g2.A = h->d_T + (long)half * gc * n2; g2.lda = n; g2.sA = n2;
+                    g2.B = h->d_F + (long)half * gc * n2; g2.ldb = n; g2.sB = n2;
+                    g2.C = h->d_Kt; g2.ldc = n; g2.sC = 0;
+                    g2.nbatch = gc; g2.alpha = h->d_Gw + g0; g2.alpha0 = 1.0; g2.reduce = 1;
+                    int tiles = ((n + 127) / 128) * ((n + 127) / 128);
+                    g2.slices = std::max(1, std::min(gc, 2048 / std::max(1, tiles)));
+                    HIPCHK(launch_dgemm(g2, st));
+                }
+            }
+        }
+    }
+    HIPCHK(hipEventRecord(h->ev[2], st));
+
+    // B7: self term -(pi/(V w^2)) S_bra S_ket
+    if (h->parts & PBC_JK_PART_SELF) {
+        const double f = -kPi / (S.lat.V * S.omega * S.omega);
+        if (wantJ) {
+            HIPCHK(launch_fill(h->d_scal, 1, 0.0, st));
+            HIPCHK(launch_dot(h->d_S, h->d_Dt, n2, h->d_scal, st));
+            HIPCHK(launch_axpy_scaled(h->d_Jt, h->d_S, n2, f, h->d_scal, st));
+        }
+        if (wantK) {
+            GemmArgs g1{};
+            g1.M = g1.N = g1.K = n;
+            g1.A = h->d_S; g1.lda = n; g1.sA = 0;
+            g1.B = h->d_Dt; g1.ldb = n; g1.sB = 0;
+            g1.C = h->d_T; g1.ldc = n; g1.sC = 0;
+            g1.nbatch = 1; g1.alpha0 = 1.0; g1.reduce = 0; g1.slices = 1;
+            HIPCHK(launch_dgemm(g1, st));
+            GemmArgs g2 = g1;
+            g2.A = h->d_T; g2.B = h->d_S; g2.C = h->d_Kt; g2.alpha0 = f; g2.reduce = 1;
+            HIPCHK(launch_dgemm(g2, st));
+        }
+    }
+
+    // B8: symmetrise, back-transform, energies
+    if (wantJ) {
+        FinalArgs fa{h->d_X, h->d_Jt, n, nb, h->d_inv_ci, h->d_inv_cc, Jo};
+        HIPCHK(launch_final(fa, st));
+    }
+    if (wantK) {
+        FinalArgs fa{h->d_Y, h->d_Kt, n, nb, h->d_inv_ci, h->d_inv_cc, Ko};
+        HIPCHK(launch_final(fa, st));
+    }
+    if (E_J || E_K) {
+        HIPCHK(launch_fill(h->d_scal + 1, 2, 0.0, st));
+        if (E_J) HIPCHK(launch_dot(dD, Jo, m2, h->d_scal + 1, st));
+        if (E_K) HIPCHK(launch_dot(dD, Ko, m2, h->d_scal + 2, st));
+    }
+    HIPCHK(hipEventRecord(h->ev[3], st));
+    h->timed = true;
+    if (E_J || E_K) {
+        double e[2];
+        HIPCHK(hipMemcpyAsync(e, h->d_scal + 1, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (E_J) *E_J = 0.5 * e[0];
+        if (E_K) *E_K = -0.25 * e[1];
+    }
+    return 0;
+}
+
+bool finite_all(const double *p, size_t n)
+{
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pbc_jk_last_error(void) { return g_err.c_str(); }
+
+int pbc_jk_create(const pbc_cell *cell, const pbc_atoms *atoms, const pbc_basis *basis, double omega,
+                  const pbc_jk_thresholds *thr, pbc_jk **out)
+{
+    g_err.clear();
+    if (!out) return fail(PBC_JK_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!cell || !atoms || !basis) return fail(PBC_JK_EINVAL, "cell, atoms and basis are required");
+    auto t0 = std::chrono::steady_clock::now();
+    double th[8] = {1e-14, 1e-14, 1e-14, 1e-14, 1e-14, 0.0, 0.0, 0.0};
+    if (thr) {
+        th[0] = thr->pair_R; th[1] = thr->pair_cs; th[2] = thr->ewald_R; th[3] = thr->ewald_K;
+        th[4] = thr->schwarz; th[5] = thr->fp32_below; th[6] = thr->r_cut; th[7] = thr->g_cut;
+    }
+    pbc_jk *h = new (std::nothrow) pbc_jk();
+    if (!h) return fail(PBC_JK_ENOMEM, "host allocation failed");
+    std::string err;
+    int rc;
+    try {
+        rc = build_setup(cell->a, atoms->natom, atoms->xyz, basis->nshell, basis->atom, basis->l, basis->pure,
+                         basis->nprim, basis->exps, basis->coefs, omega, th, h->S, err);
+    } catch (const std::bad_alloc &) {
+        delete h;
+        return fail(PBC_JK_ENOMEM, "host allocation failed during setup");
+    }
+    if (rc) {
+        delete h;
+        return fail(PBC_JK_EINVAL, err);
+    }
+#if !PBCJK_WITH_D
+    for (int s = 0; s < h->S.nshell; ++s)
+        if (h->S.sh_l[s] == 2) {
+            delete h;
+            return fail(PBC_JK_ENOTSUP, "d shells are not supported by this build");
+        }
+#endif
+    if (h->S.fp32_below > 0) {
+        delete h;
+        return fail(PBC_JK_ENOTSUP, "mixed precision (fp32_below > 0) is not available in this build");
+    }
+    rc = create_device(h);
+    if (rc) {
+        std::string keep = g_err;
+        release(h);
+        delete h;
+        g_err = keep;
+        return rc;
+    }
+    const Setup &S = h->S;
+    h->st.nbf = S.nbf; h->st.nbf_cart = S.nbfc; h->st.n_pairs = (long)S.pairs.size();
+    h->st.n_groups = (long)S.groups.size(); h->st.n_gvec = (int)S.Gw.size(); h->st.omega = S.omega;
+    h->st.t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = h;
+    return 0;
+}
+
+int pbc_jk_build_device(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, double *E_K,
+                        void *stream)
+{
+    g_err.clear();
+    if (!h) return fail(PBC_JK_EINVAL, "handle is NULL");
+    if (!dD) return fail(PBC_JK_EINVAL, "D is NULL");
+    HIPCHK(hipSetDevice(h->device));
+    auto t0 = std::chrono::steady_clock::now();
+    int rc = run_build(h, dD, dJ, dK, E_J, E_K, (hipStream_t)stream);
+    h->st.t_build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return rc;
+}
+
+int pbc_jk_build(pbc_jk *h, const double *D, double *J, double *K, double *E_J, double *E_K)
+{
+    g_err.clear();
+    if (!h) return fail(PBC_JK_EINVAL, "handle is NULL");
+    if (!D) return fail(PBC_JK_EINVAL, "D is NULL");
+    const int nb = h->S.nbf;
+    const size_t m2 = (size_t)nb * nb;
+    if (!finite_all(D, m2)) return fail(PBC_JK_EINVAL, "D has a non-finite entry");
+    double dmax = 0;
+    for (size_t i = 0; i < m2; ++i) dmax = std::max(dmax, std::fabs(D[i]));
+    for (int i = 0; i < nb; ++i)
+        for (int j = 0; j < i; ++j)
+            if (std::fabs(D[(size_t)i * nb + j] - D[(size_t)j * nb + i]) > 1e-10 * dmax)
+                return fail(PBC_JK_EINVAL, "D is not symmetric");
+    HIPCHK(hipSetDevice(h->device));
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t st = h->own;
+    HIPCHK(hipMemcpyAsync(h->d_D, D, m2 * sizeof(double), hipMemcpyHostToDevice, st));
+    double ej = 0, ek = 0;
+    int rc = run_build(h, h->d_D, J ? h->d_Jo : nullptr, K ? h->d_Ko : nullptr, E_J ? &ej : nullptr,
+                       E_K ? &ek : nullptr, st);
+    if (rc) return rc;
+    if (J) HIPCHK(hipMemcpyAsync(J, h->d_Jo, m2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (K) HIPCHK(hipMemcpyAsync(K, h->d_Ko, m2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (E_J) *E_J = ej;
+    if (E_K) *E_K = ek;
+    h->st.t_build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return 0;
+}
+
+void pbc_jk_destroy(pbc_jk *h)
+{
+    if (!h) return;
+    (void)hipSetDevice(h->device);
+    if (h->own) (void)hipStreamSynchronize(h->own);
+    release(h);
+    delete h;
+}
+
+int pbc_jk_nbf(const pbc_jk *h)
+{
+    if (!h) return fail(PBC_JK_EINVAL, "handle is NULL");
+    return h->S.nbf;
+}
+
+int pbc_jk_set_parts(pbc_jk *h, int mask)
+{
+    if (!h) return fail(PBC_JK_EINVAL, "handle is NULL");
+    if (mask & ~7) return fail(PBC_JK_EINVAL, "unknown part bits");
+    h->parts = mask;
+    return 0;
+}
+
+int pbc_jk_stats(const pbc_jk *hc, pbc_jk_counters *out)
+{
+    if (!hc || !out) return fail(PBC_JK_EINVAL, "handle or out is NULL");
+    pbc_jk *h = const_cast<pbc_jk *>(hc);
+    if (h->timed) {
+        HIPCHK(hipSetDevice(h->device));
+        HIPCHK(hipEventSynchronize(h->ev[3]));
+        float a = 0, b = 0, c = 0;
+        HIPCHK(hipEventElapsedTime(&a, h->ev[0], h->ev[1]));
+        HIPCHK(hipEventElapsedTime(&b, h->ev[1], h->ev[2]));
+        HIPCHK(hipEventElapsedTime(&c, h->ev[2], h->ev[3]));
+        h->st.t_sr_ms = a; h->st.t_lr_ms = b; h->st.t_other_ms = c;
+        unsigned long long cnt[2];
+        HIPCHK(hipMemcpy(cnt, h->d_cnt, sizeof cnt, hipMemcpyDeviceToHost));
+        h->st.quartets = (double)cnt[0];
+        h->st.terms = (double)cnt[1];
+    }
+    *out = h->st;
+    return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,100 @@
+// Kernel argument blocks and launchers (host-callable).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace pbcjk {
+
+struct SRArgs {
+    const PairRec *pairs;
+    const GroupRec *groups;
+    int gb0, nb;          // bra class: group range [gb0, gb0 + nb)
+    int gk0, nk;          // ket class: group range [gk0, gk0 + nk)
+    int tri;              // same class: only ket index >= bra index
+    const double *Dt;     // scaled Cartesian density, nbfc x nbfc
+    const double *Dmax;   // nshell x nshell block maxima of the Cartesian density
+    const double *dmax_glob;
+    double *X, *Y;        // J and K halves, nbfc x nbfc
+    int nbfc, nshell;
+    double M[9], Minv[9], span[3];
+    double w2, d_schwarz, d_ewald_R, rcap2;
+    const double *boys;   // kBoysNT x kBoysM
+    unsigned long long *counters;   // [0] primitive quartets, [1] (quartet, R1) terms
+};
+
+hipError_t launch_sr_jk(int cb, int ck, const SRArgs &a, hipStream_t st);
+
+// ---- long range and utilities (lr.hip)
+
+// Structure factors of a chunk of reciprocal vectors: F[b][mu][nu] for
+// b < ng the real parts, b in [ng, 2ng) the imaginary parts.
+struct SfacArgs {
+    const PairRec *pairs;
+    const int *sp_start, *sp_pairs, *sp_shA, *sp_shB;
+    const int *sh_l, *sh_aoc;
+    int nsp;
+    const double *G;      // 3 * ng
+    int ng;
+    double *F;            // 2 ng x nbfc x nbfc
+    int nbfc;
+};
+hipError_t launch_sfac(const SfacArgs &a, hipStream_t st);
+
+// rho[b] = sum_{mu nu} Dt[mu nu] F[b][mu nu] for b < nb.
+hipError_t launch_dot_batched(const double *F, const double *Dt, int n2, int nb, double *rho, hipStream_t st);
+
+// Jt[mu nu] += sum_g Gw[g] (F[g][mu nu] rho[g] + F[ng+g][mu nu] rho[ng+g]).
+hipError_t launch_jlr(const double *F, const double *rho, const double *Gw, int ng, int n2, double *Jt,
+                      hipStream_t st);
+
+// C_b = alpha_b A_b B_b (mode 0) or C += sum_b alpha_b A_b B_b (mode 1,
+// batches split into `slices` partial sums added atomically).  Row-major.
+struct GemmArgs {
+    int M, N, K;
+    const double *A; long lda, sA;
+    const double *B; long ldb, sB;
+    double *C; long ldc, sC;
+    int nbatch;
+    const double *alpha;  // device, per batch; NULL = 1
+    double alpha0;        // scalar factor applied on top
+    int reduce;
+    int slices;
+};
+hipError_t launch_dgemm(const GemmArgs &a, hipStream_t st);
+
+hipError_t launch_fill(double *p, long n, double v, hipStream_t st);
+
+// Density preparation: Dt (scaled Cartesian), Dc block maxima per shell pair
+// and their global maximum (as the bit pattern of a non-negative double).
+struct DprepArgs {
+    const double *D;      // nbf x nbf
+    int nbf, nbfc, nshell;
+    const int *tr_ao;     // 2 * nbfc
+    const double *tr_c;   // 2 * nbfc
+    const double *dscale; // nbfc
+    const int *sh_aoc, *sh_l;
+    double *Dt;           // nbfc^2
+    double *Dmax;         // nshell^2
+    unsigned long long *dmax_glob;
+};
+hipError_t launch_dprep(const DprepArgs &a, hipStream_t st);
+
+// sum_{ij} A[i] B[i] into out (atomic add).
+hipError_t launch_dot(const double *A, const double *B, long n, double *out, hipStream_t st);
+
+// Jt += f * s * S where s = *sdot (device scalar).
+hipError_t launch_axpy_scaled(double *Y, const double *X, long n, double f, const double *sdot, hipStream_t st);
+
+// Finalise: Jc = X + X^T + Jt, out[a][b] = sum T'[a][i] T'[b][j] Jc[i][j]
+// using the inverse transform lists (up to 3 entries per output AO).
+struct FinalArgs {
+    const double *X, *Jt;
+    int nbfc, nbf;
+    const int *inv_ci;     // 3 * nbf scaled-Cartesian indices (-1 = none)
+    const double *inv_cc;  // 3 * nbf coefficients
+    double *out;           // nbf^2
+};
+hipError_t launch_final(const FinalArgs &a, hipStream_t st);
+
+}  // namespace pbcjk

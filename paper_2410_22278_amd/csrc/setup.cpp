@@ -1,0 +1,431 @@
+// Host-side setup of a periodic J/K handle: validation, basis normalisation,
+// lattice, unique local primitive pairs grouped by (shell pair, image) and
+// sorted by angular-momentum class and Cauchy-Schwarz value, the half-space
+// reciprocal vectors, the Gamma overlap and the Boys table.
+//
+// The paper builds this pair data once per geometry on the CPU (Sec. 3.1);
+// so does this file.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <tuple>
+
+#include "internal.h"
+
+namespace pbcjk {
+
+namespace {
+
+double fact(int n) { double f = 1; for (int i = 2; i <= n; ++i) f *= i; return f; }
+
+// Cartesian component k of angular momentum l (x^l first).
+void comp(int l, int k, int c[3])
+{
+    int n = 0;
+    c[0] = c[1] = c[2] = 0;
+    for (int lx = l; lx >= 0; --lx)
+        for (int ly = l - lx; ly >= 0; --ly) {
+            if (n++ == k) { c[0] = lx; c[1] = ly; c[2] = l - lx - ly; return; }
+        }
+}
+
+// Normalisation of a Cartesian primitive (Sec. 2.1, eq. local_normalization)
+// split as Nbase(a, l) * rho(c): Nbase = (2a/pi)^{3/4} (4a)^{l/2} and
+// rho(c) = sqrt(2^l prod c! / prod (2c)!), which is 1 for s, p and the
+// mixed d components and 1/sqrt3 for xx, yy, zz.
+double nbase(double a, int l) { return std::pow(2.0 * a / kPi, 0.75) * std::pow(4.0 * a, 0.5 * l); }
+double rho_comp(const int c[3])
+{
+    int l = c[0] + c[1] + c[2];
+    return std::sqrt(std::pow(2.0, l) * fact(c[0]) * fact(c[1]) * fact(c[2]) /
+                     (fact(2 * c[0]) * fact(2 * c[1]) * fact(2 * c[2])));
+}
+
+void lattice_setup(const double *cell, Lattice &L)
+{
+    std::memcpy(L.M, cell, 9 * sizeof(double));
+    const double *m = cell;
+    double c00 = m[4] * m[8] - m[5] * m[7], c01 = m[5] * m[6] - m[3] * m[8], c02 = m[3] * m[7] - m[4] * m[6];
+    double det = m[0] * c00 + m[1] * c01 + m[2] * c02;
+    double inv[9] = {c00, m[2] * m[7] - m[1] * m[8], m[1] * m[5] - m[2] * m[4],
+                     c01, m[0] * m[8] - m[2] * m[6], m[2] * m[3] - m[0] * m[5],
+                     c02, m[1] * m[6] - m[0] * m[7], m[0] * m[4] - m[1] * m[3]};
+    for (int i = 0; i < 9; ++i) L.Minv[i] = inv[i] / det;
+    L.V = std::fabs(det);
+    for (int j = 0; j < 3; ++j)
+        L.span[j] = std::fabs(L.Minv[j]) + std::fabs(L.Minv[3 + j]) + std::fabs(L.Minv[6 + j]);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) L.B[3 * i + j] = 2.0 * kPi * L.Minv[3 * j + i];
+}
+
+void to_frac(const double *Minv, const double x[3], double f[3])
+{
+    for (int j = 0; j < 3; ++j) f[j] = x[0] * Minv[j] + x[1] * Minv[3 + j] + x[2] * Minv[6 + j];
+}
+
+// Lattice vectors (rows `rows`, fractional map `inv`, span of `inv`) within
+// a superset sphere around c; the caller applies the exact test.
+template <class F>
+void for_lattice_box(const double *rows, const double *inv, const double span[3], const double c[3],
+                     double r, F &&fn)
+{
+    double f[3];
+    to_frac(inv, c, f);
+    int lo[3], hi[3];
+    for (int j = 0; j < 3; ++j) {
+        lo[j] = (int)std::floor(f[j] - r * span[j]);
+        hi[j] = (int)std::ceil(f[j] + r * span[j]);
+    }
+    for (int n0 = lo[0]; n0 <= hi[0]; ++n0)
+        for (int n1 = lo[1]; n1 <= hi[1]; ++n1)
+            for (int n2 = lo[2]; n2 <= hi[2]; ++n2) {
+                double R[3];
+                for (int x = 0; x < 3; ++x) R[x] = n0 * rows[x] + n1 * rows[3 + x] + n2 * rows[6 + x];
+                fn(R, n0, n1, n2);
+            }
+}
+
+// One-axis Hermite coefficients with E^{00}_0 = 1 (Sec. 2.2 recurrences);
+// E[(i*(lb+1)+j)*(la+lb+1)+t].
+void herm1(int la, int lb, double p, double xa, double xb, double *E)
+{
+    int nt = la + lb + 1;
+    auto at = [&](int i, int j, int t) -> double & { return E[(i * (lb + 1) + j) * nt + t]; };
+    std::fill(E, E + (la + 1) * (lb + 1) * nt, 0.0);
+    double h = 0.5 / p;
+    at(0, 0, 0) = 1.0;
+    for (int i = 0; i < la; ++i)
+        for (int t = 0; t <= i + 1; ++t)
+            at(i + 1, 0, t) = (t >= 1 ? h * at(i, 0, t - 1) : 0.0) + (t <= i ? xa * at(i, 0, t) : 0.0) +
+                              (t + 1 <= i ? (t + 1) * at(i, 0, t + 1) : 0.0);
+    for (int i = 0; i <= la; ++i)
+        for (int j = 0; j < lb; ++j)
+            for (int t = 0; t <= i + j + 1; ++t)
+                at(i, j + 1, t) = (t >= 1 ? h * at(i, j, t - 1) : 0.0) + (t <= i + j ? xb * at(i, j, t) : 0.0) +
+                                  (t + 1 <= i + j ? (t + 1) * at(i, j, t + 1) : 0.0);
+}
+
+bool finite(double x) { return std::isfinite(x); }
+
+}  // namespace
+
+double boys_host(int m, double T)
+{
+    // series sum_k (2T)^k / ((2m+1)(2m+3)...(2m+2k+1)) times e^{-T}
+    long double term = 1.0L / (2 * m + 1), sum = term;
+    for (int k = 1; k < 4000; ++k) {
+        term *= 2.0L * T / (2 * m + 2 * k + 1);
+        sum += term;
+        if (term < 1e-22L * sum) break;
+    }
+    return (double)(std::exp(-(long double)T) * sum);
+}
+
+void boys_table(std::vector<double> &tab)
+{
+    tab.assign((size_t)kBoysNT * kBoysM, 0.0);
+    for (int k = 0; k < kBoysNT; ++k) {
+        long double T = k * (long double)kBoysStep;
+        // highest order by series, lower orders by downward recursion
+        int mt = kBoysM - 1;
+        long double term = 1.0L / (2 * mt + 1), sum = term;
+        for (int i = 1; i < 4000; ++i) {
+            term *= 2.0L * T / (2 * mt + 2 * i + 1);
+            sum += term;
+            if (term < 1e-24L * sum) break;
+        }
+        long double et = std::exp(-T);
+        long double F = et * sum;
+        tab[(size_t)k * kBoysM + mt] = (double)F;
+        for (int m = mt - 1; m >= 0; --m) {
+            F = (2.0L * T * F + et) / (2 * m + 1);
+            tab[(size_t)k * kBoysM + m] = (double)F;
+        }
+    }
+}
+
+int build_setup(const double *cell, int natom, const double *xyz, int nshell, const int *atom,
+                const int *l, const int *pure, const int *nprim, const double *exps,
+                const double *coefs, double omega, const double thr[8], Setup &S, std::string &err)
+{
+    // ---------------- validation
+    for (int i = 0; i < 9; ++i)
+        if (!finite(cell[i])) { err = "cell has a non-finite entry"; return -1; }
+    lattice_setup(cell, S.lat);
+    if (!(S.lat.V > 1e-8) || !finite(S.lat.V)) { err = "cell is singular"; return -1; }
+    if (natom <= 0 || !xyz) { err = "no atoms"; return -1; }
+    for (int i = 0; i < 3 * natom; ++i)
+        if (!finite(xyz[i])) { err = "atom position is not finite"; return -1; }
+    if (nshell <= 0 || !atom || !l || !nprim || !exps || !coefs) { err = "empty basis"; return -1; }
+    const char *names[5] = {"pair_R", "pair_cs", "ewald_R", "ewald_K", "schwarz"};
+    for (int i = 0; i < 5; ++i)
+        if (!(thr[i] > 0) || !finite(thr[i])) { err = std::string("threshold ") + names[i] + " must be > 0"; return -1; }
+    for (int i = 5; i < 8; ++i)
+        if (!(thr[i] >= 0) || !finite(thr[i])) { err = "fp32_below, r_cut, g_cut must be >= 0"; return -1; }
+    S.d_pair_R = thr[0]; S.d_pair_cs = thr[1]; S.d_ewald_R = thr[2]; S.d_ewald_K = thr[3];
+    S.d_schwarz = thr[4]; S.fp32_below = thr[5]; S.r_cut = thr[6]; S.g_cut = thr[7];
+    if (!finite(omega)) { err = "omega is not finite"; return -1; }
+    // Sec. 3.4, eq. omega_implementation with w = 10
+    S.omega = omega > 0 ? omega : std::pow(10.0 * kPi * kPi * kPi / (S.lat.V * S.lat.V), 1.0 / 6.0);
+
+    S.natom = natom;
+    S.xyz.assign(xyz, xyz + 3 * natom);
+    S.nshell = nshell;
+    S.sh_l.resize(nshell); S.sh_pure.resize(nshell); S.sh_atom.resize(nshell);
+    S.sh_aoc.resize(nshell); S.sh_ao.resize(nshell); S.sh_nprim.resize(nshell);
+    std::vector<int> poff(nshell + 1, 0);
+    for (int s = 0; s < nshell; ++s) {
+        if (l[s] < 0 || l[s] > kMaxL) { err = "angular momentum must be 0, 1 or 2"; return -1; }
+        if (atom[s] < 0 || atom[s] >= natom) { err = "shell atom index out of range"; return -1; }
+        if (nprim[s] < 1 || nprim[s] > 64) { err = "primitive count must be in 1..64"; return -1; }
+        poff[s + 1] = poff[s] + nprim[s];
+    }
+    std::vector<double> cnorm(poff[nshell]);
+    S.amin = 1e300;
+    int aoc = 0, ao = 0;
+    for (int s = 0; s < nshell; ++s) {
+        S.sh_l[s] = l[s];
+        S.sh_pure[s] = (pure && pure[s] && l[s] == 2) ? 1 : 0;
+        S.sh_atom[s] = atom[s];
+        S.sh_nprim[s] = nprim[s];
+        S.sh_aoc[s] = aoc; S.sh_ao[s] = ao;
+        aoc += ncart(l[s]);
+        ao += S.sh_pure[s] ? 2 * l[s] + 1 : ncart(l[s]);
+        const double *a = exps + poff[s], *c = coefs + poff[s];
+        for (int i = 0; i < nprim[s]; ++i) {
+            if (!(a[i] > 0) || !finite(a[i])) { err = "exponents must be positive and finite"; return -1; }
+            if (!finite(c[i])) { err = "contraction coefficient is not finite"; return -1; }
+            S.amin = std::min(S.amin, a[i]);
+        }
+        // unit single-centre self-overlap of the contracted shell
+        double ss = 0;
+        for (int i = 0; i < nprim[s]; ++i)
+            for (int j = 0; j < nprim[s]; ++j)
+                ss += c[i] * c[j] * std::pow(2.0 * std::sqrt(a[i] * a[j]) / (a[i] + a[j]), l[s] + 1.5);
+        if (!(ss > 0)) { err = "contracted shell has zero norm"; return -1; }
+        for (int i = 0; i < nprim[s]; ++i) cnorm[poff[s] + i] = c[i] / std::sqrt(ss);
+    }
+    S.nbfc = aoc; S.nbf = ao;
+
+    // ---------------- output transform T' = T diag(rho)
+    S.tr_ao.assign(2 * S.nbfc, -1);
+    S.tr_c.assign(2 * S.nbfc, 0.0);
+    S.dscale.assign(S.nbfc, 1.0);
+    const double h3 = std::sqrt(3.0) / 2.0;
+    for (int s = 0; s < nshell; ++s) {
+        for (int k = 0; k < ncart(l[s]); ++k) {
+            int c[3]; comp(l[s], k, c);
+            int i = S.sh_aoc[s] + k;
+            double r = rho_comp(c);
+            S.dscale[i] = r;
+            if (!S.sh_pure[s]) { S.tr_ao[2 * i] = S.sh_ao[s] + k; S.tr_c[2 * i] = r; continue; }
+            int o = S.sh_ao[s];
+            // columns of the 5 x 6 solid-harmonic matrix (xx, xy, xz, yy, yz, zz)
+            switch (k) {
+                case 0: S.tr_ao[2*i] = o + 2; S.tr_c[2*i] = -0.5 * r; S.tr_ao[2*i+1] = o + 4; S.tr_c[2*i+1] = h3 * r; break;
+                case 1: S.tr_ao[2*i] = o + 0; S.tr_c[2*i] = r; break;
+                case 2: S.tr_ao[2*i] = o + 3; S.tr_c[2*i] = r; break;
+                case 3: S.tr_ao[2*i] = o + 2; S.tr_c[2*i] = -0.5 * r; S.tr_ao[2*i+1] = o + 4; S.tr_c[2*i+1] = -h3 * r; break;
+                case 4: S.tr_ao[2*i] = o + 1; S.tr_c[2*i] = r; break;
+                case 5: S.tr_ao[2*i] = o + 2; S.tr_c[2*i] = r; break;
+            }
+        }
+    }
+
+    // ---------------- unique local primitive pairs
+    struct Tmp { int cls, first, second, n0, n1, n2; PairRec rec; };
+    std::vector<Tmp> tmp;
+    const Lattice &L = S.lat;
+    const double rcap2 = S.r_cut > 0 ? S.r_cut * S.r_cut : 0.0;
+    long ordered = 0;
+    for (int A = 0; A < nshell; ++A)
+        for (int B = A; B < nshell; ++B) {
+            // orientation: the higher angular momentum first; ties by index
+            int first = A, second = B;
+            if (l[B] > l[A]) std::swap(first, second);
+            const double *xf = xyz + 3 * atom[first], *xs = xyz + 3 * atom[second];
+            double d[3] = {xf[0] - xs[0], xf[1] - xs[1], xf[2] - xs[2]}, f[3], dmin[3];
+            to_frac(L.Minv, d, f);
+            double nr[3] = {(double)std::lround(f[0]), (double)std::lround(f[1]), (double)std::lround(f[2])};
+            for (int x = 0; x < 3; ++x)
+                dmin[x] = d[x] - (nr[0] * L.M[x] + nr[1] * L.M[3 + x] + nr[2] * L.M[6 + x]);
+            int la = l[first], lb = l[second];
+            for (int i = 0; i < nprim[first]; ++i)
+                for (int j = 0; j < nprim[second]; ++j) {
+                    if (first == second && j < i) continue;   // (i,j,R) ~ (j,i,-R)
+                    double a = exps[poff[first] + i], b = exps[poff[second] + j];
+                    double ca = cnorm[poff[first] + i], cb = cnorm[poff[second] + j];
+                    double p = a + b, mu = a * b / p;
+                    double Cab = std::fabs(ca * cb) * nbase(a, la) * nbase(b, lb);
+                    double X0 = std::sqrt(2.0) * std::pow(kPi, 1.25) * Cab / (p * std::pow(p + 2.0 * S.amin, 0.25));
+                    double Y0 = std::pow(2.0, 0.25) * std::pow(kPi, 1.25) * Cab / std::pow(p, 1.25);
+                    double lm = std::min(std::log(X0 / S.d_pair_R), std::log(Y0 / S.d_pair_cs));
+                    if (!(lm > 0)) continue;
+                    double r = std::sqrt(lm / mu) * (1.0 + 1e-9) + 1e-9;
+                    if (S.r_cut > 0) r = std::min(r, S.r_cut * (1.0 + 1e-9) + 1e-9);
+                    for_lattice_box(L.M, L.Minv, L.span, dmin, r, [&](const double R[3], int n0, int n1, int n2) {
+                        double v[3] = {dmin[0] - R[0], dmin[1] - R[1], dmin[2] - R[2]};
+                        double r2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+                        double g = std::exp(-mu * r2);
+                        if (!(X0 * g > S.d_pair_R) || !(Y0 * g > S.d_pair_cs)) return;
+                        if (rcap2 > 0 && r2 > rcap2) return;
+                        double fw = 1.0;
+                        if (first == second) {
+                            if (i == j) {
+                                bool zero = (n0 == 0 && n1 == 0 && n2 == 0);
+                                bool pos = n0 > 0 || (n0 == 0 && (n1 > 0 || (n1 == 0 && n2 > 0)));
+                                if (zero) fw = 0.5;
+                                else if (!pos) return;
+                            }
+                            ordered += (i == j && fw == 0.5) ? 1 : 2;
+                        } else {
+                            ordered += 2;
+                        }
+                        Tmp t;
+                        t.cls = class_of(la, lb); t.first = first; t.second = second;
+                        t.n0 = n0; t.n1 = n1; t.n2 = n2;
+                        double Bi[3];
+                        for (int x = 0; x < 3; ++x) {
+                            Bi[x] = xf[x] - v[x];
+                            t.rec.P[x] = (a * xf[x] + b * Bi[x]) / p;
+                            t.rec.PA[x] = t.rec.P[x] - xf[x];
+                            t.rec.PB[x] = t.rec.P[x] - Bi[x];
+                        }
+                        t.rec.p = p;
+                        t.rec.cpre = ca * cb * nbase(a, la) * nbase(b, lb) * g * fw;
+                        t.rec.Q = Y0 * g;
+                        t.rec.Cb = Cab * g;
+                        t.rec.pad[0] = t.rec.pad[1] = t.rec.pad[2] = 0.0;
+                        tmp.push_back(t);
+                    });
+                }
+        }
+    S.n_pairs_ordered = ordered;
+
+    // ---------------- groups: (class, first, second, image); class asc, Qmax desc
+    std::vector<size_t> idx(tmp.size());
+    std::iota(idx.begin(), idx.end(), 0);
+    auto gkey = [&](const Tmp &t) { return std::make_tuple(t.cls, t.first, t.second, t.n0, t.n1, t.n2); };
+    std::sort(idx.begin(), idx.end(), [&](size_t x, size_t y) {
+        auto kx = gkey(tmp[x]), ky = gkey(tmp[y]);
+        if (kx != ky) return kx < ky;
+        return tmp[x].rec.Q > tmp[y].rec.Q;
+    });
+    struct G0 { size_t b, e; double qmax; int cls; };
+    std::vector<G0> gl;
+    for (size_t k = 0; k < idx.size();) {
+        size_t e = k;
+        double qm = 0;
+        while (e < idx.size() && gkey(tmp[idx[e]]) == gkey(tmp[idx[k]])) {
+            qm = std::max(qm, tmp[idx[e]].rec.Q);
+            ++e;
+        }
+        gl.push_back({k, e, qm, tmp[idx[k]].cls});
+        k = e;
+    }
+    std::vector<size_t> gord(gl.size());
+    std::iota(gord.begin(), gord.end(), 0);
+    std::stable_sort(gord.begin(), gord.end(), [&](size_t x, size_t y) {
+        if (gl[x].cls != gl[y].cls) return gl[x].cls < gl[y].cls;
+        return gl[x].qmax > gl[y].qmax;
+    });
+    S.pairs.clear(); S.groups.clear();
+    S.pairs.reserve(tmp.size()); S.groups.reserve(gl.size());
+    for (int c = 0; c <= kNumClass; ++c) S.class_start[c] = 0;
+    for (size_t gi : gord) {
+        const G0 &g = gl[gi];
+        const Tmp &t0 = tmp[idx[g.b]];
+        GroupRec G;
+        G.shA = t0.first; G.shB = t0.second;
+        G.aoA = S.sh_aoc[t0.first]; G.aoB = S.sh_aoc[t0.second];
+        G.pstart = (int)S.pairs.size();
+        for (size_t k = g.b; k < g.e; ++k) S.pairs.push_back(tmp[idx[k]].rec);
+        G.pend = (int)S.pairs.size();
+        G.Qmax = g.qmax; G.pad = 0.0;
+        S.groups.push_back(G);
+        S.class_start[g.cls + 1]++;
+    }
+    for (int c = 0; c < kNumClass; ++c) S.class_start[c + 1] += S.class_start[c];
+
+    // unique shell pairs with their pair indices (for the structure factors)
+    {
+        std::vector<std::pair<std::pair<int, int>, int>> sp;
+        sp.reserve(S.pairs.size());
+        for (const GroupRec &G : S.groups)
+            for (int k = G.pstart; k < G.pend; ++k) sp.push_back({{G.shA, G.shB}, k});
+        std::sort(sp.begin(), sp.end());
+        S.sp_start.clear(); S.sp_pairs.clear(); S.sp_shA.clear(); S.sp_shB.clear();
+        for (size_t k = 0; k < sp.size(); ++k) {
+            if (k == 0 || sp[k].first != sp[k - 1].first) {
+                S.sp_start.push_back((int)k);
+                S.sp_shA.push_back(sp[k].first.first);
+                S.sp_shB.push_back(sp[k].first.second);
+            }
+            S.sp_pairs.push_back(sp[k].second);
+        }
+        S.sp_start.push_back((int)sp.size());
+    }
+
+    // ---------------- reciprocal vectors (half space), weights 2 w_G
+    {
+        auto wfun = [&](double G2) { return 4.0 * kPi / L.V * std::exp(-G2 / (4.0 * S.omega * S.omega)) / G2; };
+        double lo = 1e-6, hi = 1.0;
+        while (wfun(hi * hi) > S.d_ewald_K) hi *= 2.0;
+        for (int it = 0; it < 200; ++it) {
+            double mid = 0.5 * (lo + hi);
+            if (wfun(mid * mid) > S.d_ewald_K) lo = mid; else hi = mid;
+        }
+        double r = hi * (1.0 + 1e-9);
+        if (S.g_cut > 0 && S.g_cut < r) r = S.g_cut * (1.0 + 1e-9);
+        double Binv[9], bspan[3];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) Binv[3 * i + j] = L.M[3 * j + i] / (2.0 * kPi);
+        for (int j = 0; j < 3; ++j) bspan[j] = std::fabs(Binv[j]) + std::fabs(Binv[3 + j]) + std::fabs(Binv[6 + j]);
+        double zero[3] = {0, 0, 0};
+        S.G.clear(); S.Gw.clear();
+        for_lattice_box(L.B, Binv, bspan, zero, r, [&](const double Gv[3], int n0, int n1, int n2) {
+            bool pos = n0 > 0 || (n0 == 0 && (n1 > 0 || (n1 == 0 && n2 > 0)));
+            if (!pos) return;
+            double G2 = Gv[0] * Gv[0] + Gv[1] * Gv[1] + Gv[2] * Gv[2];
+            double w = wfun(G2);
+            if (!(w > S.d_ewald_K)) return;
+            if (S.g_cut > 0 && G2 > S.g_cut * S.g_cut) return;
+            S.G.push_back(Gv[0]); S.G.push_back(Gv[1]); S.G.push_back(Gv[2]);
+            S.Gw.push_back(2.0 * w);
+        });
+    }
+
+    // ---------------- Gamma overlap in the scaled Cartesian basis (Sec. 2.2)
+    S.S.assign((size_t)S.nbfc * S.nbfc, 0.0);
+    {
+        std::vector<double> Sh((size_t)S.nbfc * S.nbfc, 0.0);
+        double Ex[45], Ey[45], Ez[45];   // (lmax+1)^2 (2 lmax+1) entries per axis
+        for (const GroupRec &G : S.groups) {
+            int la = l[G.shA], lb = l[G.shB], nt = la + lb + 1;
+            for (int k = G.pstart; k < G.pend; ++k) {
+                const PairRec &P = S.pairs[k];
+                herm1(la, lb, P.p, P.PA[0], P.PB[0], Ex);
+                herm1(la, lb, P.p, P.PA[1], P.PB[1], Ey);
+                herm1(la, lb, P.p, P.PA[2], P.PB[2], Ez);
+                double pre = P.cpre * std::pow(kPi / P.p, 1.5);
+                for (int ia = 0; ia < ncart(la); ++ia) {
+                    int ca[3]; comp(la, ia, ca);
+                    for (int ib = 0; ib < ncart(lb); ++ib) {
+                        int cb[3]; comp(lb, ib, cb);
+                        double v = pre * Ex[(ca[0] * (lb + 1) + cb[0]) * nt] * Ey[(ca[1] * (lb + 1) + cb[1]) * nt] *
+                                   Ez[(ca[2] * (lb + 1) + cb[2]) * nt];
+                        Sh[(size_t)(G.aoA + ia) * S.nbfc + G.aoB + ib] += v;
+                    }
+                }
+            }
+        }
+        for (int i = 0; i < S.nbfc; ++i)
+            for (int j = 0; j < S.nbfc; ++j)
+                S.S[(size_t)i * S.nbfc + j] = Sh[(size_t)i * S.nbfc + j] + Sh[(size_t)j * S.nbfc + i];
+    }
+    boys_table(S.boys);
+    return 0;
+}
+
+}  // namespace pbcjk

@@ -1,0 +1,231 @@
+"""ctypes binding of libpbcjk.so (include/pbcjk.h): argument marshalling only.
+
+Every step of a build runs in the HIP library; this module only converts
+numpy arrays and torch device tensors into pointers.  Loading fails loudly
+when the built library is missing (run __graft_entry__.build()).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_char_p, c_double, c_int, c_long, c_void_p
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpbcjk.so")
+
+PBC_JK_OK = 0
+PBC_JK_EINVAL = -1
+PBC_JK_ENOMEM = -2
+PBC_JK_EDEVICE = -3
+PBC_JK_ENOTSUP = -4
+PART_SR, PART_LR, PART_SELF = 1, 2, 4
+
+# every symbol the header declares
+EXPORTS = ["pbc_jk_create", "pbc_jk_build", "pbc_jk_build_device", "pbc_jk_destroy",
+           "pbc_jk_nbf", "pbc_jk_stats", "pbc_jk_set_parts", "pbc_jk_last_error"]
+
+
+class pbc_cell(ctypes.Structure):
+    _fields_ = [("a", c_double * 9)]
+
+
+class pbc_atoms(ctypes.Structure):
+    _fields_ = [("natom", c_int), ("xyz", POINTER(c_double)), ("charge", POINTER(c_double))]
+
+
+class pbc_basis(ctypes.Structure):
+    _fields_ = [("nshell", c_int), ("atom", POINTER(c_int)), ("l", POINTER(c_int)),
+                ("pure", POINTER(c_int)), ("nprim", POINTER(c_int)),
+                ("exps", POINTER(c_double)), ("coefs", POINTER(c_double))]
+
+
+class pbc_jk_thresholds(ctypes.Structure):
+    _fields_ = [("pair_R", c_double), ("pair_cs", c_double), ("ewald_R", c_double),
+                ("ewald_K", c_double), ("schwarz", c_double), ("fp32_below", c_double),
+                ("r_cut", c_double), ("g_cut", c_double)]
+
+
+class pbc_jk_counters(ctypes.Structure):
+    _fields_ = [("nbf", c_int), ("nbf_cart", c_int), ("n_pairs", c_long), ("n_groups", c_long),
+                ("n_gvec", c_int), ("omega", c_double), ("quartets", c_double),
+                ("terms", c_double), ("terms_fp32", c_double), ("t_setup_ms", c_double),
+                ("t_build_ms", c_double), ("t_sr_ms", c_double), ("t_lr_ms", c_double),
+                ("t_other_ms", c_double)]
+
+
+class PbcJkError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"pbcjk error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Loads libpbcjk.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    lib.pbc_jk_create.argtypes = [POINTER(pbc_cell), POINTER(pbc_atoms), POINTER(pbc_basis), c_double,
+                                  POINTER(pbc_jk_thresholds), POINTER(c_void_p)]
+    lib.pbc_jk_create.restype = c_int
+    lib.pbc_jk_build.argtypes = [c_void_p, POINTER(c_double), POINTER(c_double), POINTER(c_double),
+                                 POINTER(c_double), POINTER(c_double)]
+    lib.pbc_jk_build.restype = c_int
+    lib.pbc_jk_build_device.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_double),
+                                        POINTER(c_double), c_void_p]
+    lib.pbc_jk_build_device.restype = c_int
+    lib.pbc_jk_destroy.argtypes = [c_void_p]
+    lib.pbc_jk_destroy.restype = None
+    lib.pbc_jk_nbf.argtypes = [c_void_p]
+    lib.pbc_jk_nbf.restype = c_int
+    lib.pbc_jk_stats.argtypes = [c_void_p, POINTER(pbc_jk_counters)]
+    lib.pbc_jk_stats.restype = c_int
+    lib.pbc_jk_set_parts.argtypes = [c_void_p, c_int]
+    lib.pbc_jk_set_parts.restype = c_int
+    lib.pbc_jk_last_error.argtypes = []
+    lib.pbc_jk_last_error.restype = c_char_p
+    _lib = lib
+    return lib
+
+
+def pbc_jk_last_error() -> str:
+    return load().pbc_jk_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != PBC_JK_OK:
+        raise PbcJkError(rc, pbc_jk_last_error())
+
+
+def _dp(a):
+    return a.ctypes.data_as(POINTER(c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(POINTER(c_int))
+
+
+def pbc_jk_create(cell, xyz, shell_atom, shell_l, shell_pure, shell_nprim, exps, coefs,
+                  omega: float, thr=None) -> int:
+    """Returns the opaque handle (an integer address)."""
+    lib = load()
+    c = pbc_cell()
+    c.a[:] = [float(x) for x in np.asarray(cell, dtype=np.float64).ravel()]
+    keep = [np.ascontiguousarray(xyz, dtype=np.float64),
+            np.ascontiguousarray(shell_atom, dtype=np.int32),
+            np.ascontiguousarray(shell_l, dtype=np.int32),
+            np.ascontiguousarray(shell_pure, dtype=np.int32),
+            np.ascontiguousarray(shell_nprim, dtype=np.int32),
+            np.ascontiguousarray(exps, dtype=np.float64),
+            np.ascontiguousarray(coefs, dtype=np.float64)]
+    at = pbc_atoms(keep[0].shape[0], _dp(keep[0]), None)
+    bs = pbc_basis(keep[1].shape[0], _ip(keep[1]), _ip(keep[2]), _ip(keep[3]), _ip(keep[4]),
+                   _dp(keep[5]), _dp(keep[6]))
+    th = None
+    if thr is not None:
+        th = pbc_jk_thresholds(thr.pair_R, thr.pair_cs, thr.ewald_R, thr.ewald_K, thr.schwarz,
+                               thr.fp32_below, thr.r_cut, thr.g_cut)
+    h = c_void_p()
+    rc = lib.pbc_jk_create(byref(c), byref(at), byref(bs), float(omega),
+                           byref(th) if th is not None else None, byref(h))
+    _check(rc)
+    return h.value
+
+
+def pbc_jk_build(h: int, D, want_J: bool = True, want_K: bool = True):
+    """Host-memory build: returns (J, K, E_J, E_K)."""
+    lib = load()
+    D = np.ascontiguousarray(D, dtype=np.float64)
+    n = D.shape[0]
+    J = np.empty((n, n)) if want_J else None
+    K = np.empty((n, n)) if want_K else None
+    ej, ek = c_double(), c_double()
+    rc = lib.pbc_jk_build(c_void_p(h), _dp(D), _dp(J) if J is not None else None,
+                          _dp(K) if K is not None else None, byref(ej), byref(ek))
+    _check(rc)
+    return J, K, ej.value, ek.value
+
+
+def pbc_jk_build_device(h: int, dD, dJ=None, dK=None, energies: bool = True, stream=None):
+    """Device-memory build on torch tensors (float64, cuda, contiguous).
+    Returns (E_J, E_K) when energies, else None (asynchronous)."""
+    lib = load()
+    for t in (dD, dJ, dK):
+        if t is not None and (t.dtype.itemsize != 8 or not t.is_cuda or not t.is_contiguous()):
+            raise ValueError("device buffers must be contiguous float64 cuda tensors")
+    ej, ek = c_double(), c_double()
+    sp = None
+    if stream is not None:
+        sp = c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+    rc = lib.pbc_jk_build_device(c_void_p(h), c_void_p(dD.data_ptr()),
+                                 c_void_p(dJ.data_ptr()) if dJ is not None else None,
+                                 c_void_p(dK.data_ptr()) if dK is not None else None,
+                                 byref(ej) if energies else None, byref(ek) if energies else None, sp)
+    _check(rc)
+    return (ej.value, ek.value) if energies else None
+
+
+def pbc_jk_destroy(h: int):
+    if h:
+        load().pbc_jk_destroy(c_void_p(h))
+
+
+def pbc_jk_nbf(h: int) -> int:
+    return load().pbc_jk_nbf(c_void_p(h))
+
+
+def pbc_jk_stats(h: int) -> dict:
+    s = pbc_jk_counters()
+    _check(load().pbc_jk_stats(c_void_p(h), byref(s)))
+    return {k: getattr(s, k) for k, _ in s._fields_}
+
+
+def pbc_jk_set_parts(h: int, mask: int):
+    _check(load().pbc_jk_set_parts(c_void_p(h), int(mask)))
+
+
+class Handle:
+    """Owns one library handle for a System from paper_2410_22278_amd.inputs."""
+
+    def __init__(self, system, omega=None, thr=None):
+        t = thr if thr is not None else system.thr
+        self.h = pbc_jk_create(system.cell, system.xyz, system.shell_atom, system.shell_l,
+                               system.shell_pure, system.shell_nprim, system.exps, system.coefs,
+                               system.omega if omega is None else omega, t)
+        self.nbf = pbc_jk_nbf(self.h)
+
+    def build(self, D, want_J=True, want_K=True):
+        return pbc_jk_build(self.h, D, want_J, want_K)
+
+    def build_device(self, dD, dJ=None, dK=None, energies=True, stream=None):
+        return pbc_jk_build_device(self.h, dD, dJ, dK, energies, stream)
+
+    def stats(self):
+        return pbc_jk_stats(self.h)
+
+    def set_parts(self, mask):
+        pbc_jk_set_parts(self.h, mask)
+
+    def close(self):
+        if self.h:
+            pbc_jk_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
