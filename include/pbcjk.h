@@ -117,6 +117,10 @@ typedef struct {
     double t_setup_ms;   /* create wall time                                 */
     double t_build_ms;   /* last build wall time                             */
     double t_sr_ms, t_lr_ms, t_other_ms; /* last build, device stage times   */
+    double t_gemm_ms;    /* last build: summed durations of the FP64 matrix-core GEMM launches */
+    double gemm_flops;   /* last build: algorithmic FLOPs of those launches (2 M N K each)     */
+    int n_gemm;          /* last build: number of those launches                                */
+    double t_sfac_ms;    /* last build: summed durations of the structure-factor launches      */
 } pbc_jk_counters;
 
 /* Creates a handle: validates and copies the inputs, builds the local pair

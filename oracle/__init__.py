@@ -326,11 +326,13 @@ def ao_rows(system, shells: Sequence[int]) -> np.ndarray:
 
 
 def jk(system, D=None, omega=None, thr=None, bra_shells: Optional[Sequence[int]] = None,
-       parts: str = "sr,lr,self", g_chunk: int = 64) -> dict:
+       parts: str = "sr,lr,self", g_chunk: int = 64, g_range=None) -> dict:
     """Gamma-point J and K of `system` (spherical where the basis says so).
 
     With bra_shells set, only the rows of J and K belonging to those shells
     are exact (the others are left partial); energies are then not formed.
+    g_range = (start, stop) restricts the reciprocal sum to a slice of the
+    G list (for timing samples only).
     Returns a dict with J, K, E_J, E_K, the parts, and counts."""
     D = system.D if D is None else D
     s = _Sys(system, omega, thr)
@@ -347,6 +349,8 @@ def jk(system, D=None, omega=None, thr=None, bra_shells: Optional[Sequence[int]]
     nG = 0
     if "lr" in want:
         G, w = glist(system, omega, thr)
+        if g_range is not None:
+            G, w = G[g_range[0]:g_range[1]], w[g_range[0]:g_range[1]]
         nG = G.shape[0]
         lib = _load()
         ctx = lib.orc_ctx_new(ctypes.byref(s.c))

@@ -70,6 +70,12 @@ struct pbc_jk {
     unsigned long long *d_dmaxg = nullptr, *d_cnt = nullptr;
     int gchunk = 0;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // event pairs around GEMM and structure-factor launches of one build
+    static constexpr int kMaxTimed = 256;
+    std::vector<hipEvent_t> tev;
+    std::vector<int> tkind;      // 0 = GEMM, 1 = structure factors
+    std::vector<double> tflops;
+    int ntimed = 0;
     bool timed = false;
     pbc_jk_counters st{};
 };
@@ -86,8 +92,30 @@ void release(pbc_jk *h)
         if (p) (void)hipFree(p);
     for (auto &e : h->ev)
         if (e) (void)hipEventDestroy(e);
+    for (auto &e : h->tev)
+        if (e) (void)hipEventDestroy(e);
     if (h->own) (void)hipStreamDestroy(h->own);
 }
+
+// Brackets one launch with a pair of events (up to kMaxTimed per build).
+struct TimedLaunch {
+    pbc_jk *h;
+    hipStream_t st;
+    int slot = -1;
+    TimedLaunch(pbc_jk *h_, hipStream_t st_, int kind, double flops) : h(h_), st(st_)
+    {
+        if (h->ntimed < pbc_jk::kMaxTimed) {
+            slot = h->ntimed++;
+            h->tkind[slot] = kind;
+            h->tflops[slot] = flops;
+            (void)hipEventRecord(h->tev[2 * slot], st);
+        }
+    }
+    ~TimedLaunch()
+    {
+        if (slot >= 0) (void)hipEventRecord(h->tev[2 * slot + 1], st);
+    }
+};
 
 int create_device(pbc_jk *h)
 {
@@ -95,6 +123,10 @@ int create_device(pbc_jk *h)
     HIPCHK(hipGetDevice(&h->device));
     HIPCHK(hipStreamCreateWithFlags(&h->own, hipStreamNonBlocking));
     for (auto &e : h->ev) HIPCHK(hipEventCreate(&e));
+    h->tev.assign(2 * pbc_jk::kMaxTimed, nullptr);
+    h->tkind.assign(pbc_jk::kMaxTimed, 0);
+    h->tflops.assign(pbc_jk::kMaxTimed, 0.0);
+    for (auto &e : h->tev) HIPCHK(hipEventCreate(&e));
     int rc;
     if ((rc = upload(&h->d_pairs, S.pairs))) return rc;
     if ((rc = upload(&h->d_groups, S.groups))) return rc;
@@ -160,6 +192,7 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
     const bool wantJ = dJ || E_J, wantK = dK || E_K;
     double *Jo = dJ ? dJ : h->d_Jo;
     double *Ko = dK ? dK : h->d_Ko;
+    h->ntimed = 0;
     HIPCHK(hipEventRecord(h->ev[0], st));
 
     // B1: density in the scaled Cartesian basis, block maxima
@@ -209,7 +242,10 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
             const int gc = std::min(h->gchunk, nG - g0);
             HIPCHK(launch_fill(h->d_F, 2L * gc * n2, 0.0, st));
             sa.G = h->d_G + 3 * g0; sa.ng = gc;
-            HIPCHK(launch_sfac(sa, st));
+            {
+                TimedLaunch tl(h, st, 1, 0.0);
+                HIPCHK(launch_sfac(sa, st));
+            }
             if (wantJ) {
                 HIPCHK(launch_dot_batched(h->d_F, h->d_Dt, (int)n2, 2 * gc, h->d_rho, st));
                 HIPCHK(launch_jlr(h->d_F, h->d_rho, h->d_Gw + g0, gc, (int)n2, h->d_Jt, st));
@@ -221,7 +257,10 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
                 g1.B = h->d_Dt; g1.ldb = n; g1.sB = 0;
                 g1.C = h->d_T; g1.ldc = n; g1.sC = n2;
                 g1.nbatch = 2 * gc; g1.alpha = nullptr; g1.alpha0 = 1.0; g1.reduce = 0; g1.slices = 1;
-                HIPCHK(launch_dgemm(g1, st));
+                {
+                    TimedLaunch tl(h, st, 0, 2.0 * n * (double)n * n * g1.nbatch);
+                    HIPCHK(launch_dgemm(g1, st));
+                }
                 // K_LR += sum_b W_b T_b F_b; weights repeat for the real and imaginary halves
                 for (int half = 0; half < 2; ++half) {
                     GemmArgs g2{};
@@ -232,6 +271,7 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
                     g2.nbatch = gc; g2.alpha = h->d_Gw + g0; g2.alpha0 = 1.0; g2.reduce = 1;
                     int tiles = ((n + 127) / 128) * ((n + 127) / 128);
                     g2.slices = std::max(1, std::min(gc, 2048 / std::max(1, tiles)));
+                    TimedLaunch tl(h, st, 0, 2.0 * n * (double)n * n * g2.nbatch);
                     HIPCHK(launch_dgemm(g2, st));
                 }
             }
@@ -438,6 +478,19 @@ int pbc_jk_stats(const pbc_jk *hc, pbc_jk_counters *out)
         HIPCHK(hipMemcpy(cnt, h->d_cnt, sizeof cnt, hipMemcpyDeviceToHost));
         h->st.quartets = (double)cnt[0];
         h->st.terms = (double)cnt[1];
+        h->st.t_gemm_ms = h->st.t_sfac_ms = h->st.gemm_flops = 0.0;
+        h->st.n_gemm = 0;
+        for (int i = 0; i < h->ntimed; ++i) {
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, h->tev[2 * i], h->tev[2 * i + 1]));
+            if (h->tkind[i] == 0) {
+                h->st.t_gemm_ms += ms;
+                h->st.gemm_flops += h->tflops[i];
+                h->st.n_gemm++;
+            } else {
+                h->st.t_sfac_ms += ms;
+            }
+        }
     }
     *out = h->st;
     return 0;

@@ -257,6 +257,8 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs a)
 // Block tile 128 x 128, four waves in a 2 x 2 arrangement, each owning a
 // 64 x 64 sub-tile as 4 x 4 MFMA 16x16x4 accumulators; K staged through LDS
 // in slabs of 16 with the next slab prefetched into registers.
+// Operand layout of v_mfma_f64_16x16x4f64 (lane l): A[l & 15][l >> 4],
+// B[l >> 4][l & 15]; result register r holds D[(l >> 4) + 4 r][l & 15].
 constexpr int GBM = 128, GBN = 128, GBK = 16, GPAD = 2;
 
 __global__ __launch_bounds__(256) void k_dgemm(GemmArgs g)
@@ -337,7 +339,7 @@ __global__ __launch_bounds__(256) void k_dgemm(GemmArgs g)
                 for (int j = 0; j < 4; ++j)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        int gm = m0 + wm * 64 + i * 16 + lk * 4 + r;
+                        int gm = m0 + wm * 64 + i * 16 + lk + 4 * r;
                         int gn = n0 + wn * 64 + j * 16 + lr;
                         if (gm < g.M && gn < g.N) C[(long)gm * g.ldc + gn] = acc[i][j][r];
                     }
@@ -350,7 +352,7 @@ __global__ __launch_bounds__(256) void k_dgemm(GemmArgs g)
             for (int j = 0; j < 4; ++j)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    int gm = m0 + wm * 64 + i * 16 + lk * 4 + r;
+                    int gm = m0 + wm * 64 + i * 16 + lk + 4 * r;
                     int gn = n0 + wn * 64 + j * 16 + lr;
                     if (gm < g.M && gn < g.N) atomicAdd(&g.C[(long)gm * g.ldc + gn], acc[i][j][r]);
                 }

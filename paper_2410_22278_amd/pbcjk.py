@@ -52,7 +52,8 @@ class pbc_jk_counters(ctypes.Structure):
                 ("n_gvec", c_int), ("omega", c_double), ("quartets", c_double),
                 ("terms", c_double), ("terms_fp32", c_double), ("t_setup_ms", c_double),
                 ("t_build_ms", c_double), ("t_sr_ms", c_double), ("t_lr_ms", c_double),
-                ("t_other_ms", c_double)]
+                ("t_other_ms", c_double), ("t_gemm_ms", c_double), ("gemm_flops", c_double),
+                ("n_gemm", c_int), ("t_sfac_ms", c_double)]
 
 
 class PbcJkError(RuntimeError):

@@ -60,9 +60,16 @@ def test_small_cells(lib, oracle_mod, case):
     assert dJ < 1e-9 and dK < 1e-9 and dEJ < 1e-9 and dEK < 1e-9
 
 
+PART_CASES = [dict(seed=5, natom=3, recipe=((0, 0), (0, 0), (1, 0)), skew=0.15, omega=0.35),
+              dict(seed=3, natom=2, recipe=((0, 0), (1, 0)))]
+
+
 @pytest.mark.parametrize("mask,key", [(1, "sr"), (2, "lr"), (4, "self")])
-def test_parts(lib, oracle_mod, mask, key):
-    s = inputs.small_cell(5, natom=3, recipe=((0, 0), (0, 0), (1, 0)), skew=0.15, omega=0.35)
+@pytest.mark.parametrize("case", PART_CASES, ids=["nbf15", "nbf8"])
+def test_parts(lib, oracle_mod, mask, key, case):
+    """Each part alone: partial 16-row matrix-core tiles (nbf 8 and 15) make
+    any lane-layout mistake in the reciprocal and self GEMMs visible."""
+    s = inputs.small_cell(**case)
     ref = oracle_mod.jk(s, parts=key)
     with lib.Handle(s) as h:
         h.set_parts(mask)
