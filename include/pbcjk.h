@@ -121,6 +121,11 @@ typedef struct {
     double gemm_flops;   /* last build: algorithmic FLOPs of those launches (2 M N K each)     */
     int n_gemm;          /* last build: number of those launches                                */
     double t_sfac_ms;    /* last build: summed durations of the structure-factor launches      */
+    double terms_class[21]; /* last build: short-range terms per class pair, in the order
+                               (bra class, ket class) = (0,0),(0,1),..,(0,5),(1,1),..,(5,5)
+                               with classes ss, ps, pp, ds, dp, dd                      */
+    double n_group_pairs; /* entries of the real-space neighbour lists (group pairs that can
+                               have a term for some density)                            */
 } pbc_jk_counters;
 
 /* Creates a handle: validates and copies the inputs, builds the local pair

@@ -68,6 +68,9 @@ struct pbc_jk {
     double *d_Jt = nullptr, *d_Kt = nullptr, *d_F = nullptr, *d_T = nullptr, *d_rho = nullptr;
     double *d_scal = nullptr, *d_Jo = nullptr, *d_Ko = nullptr;
     unsigned long long *d_dmaxg = nullptr, *d_cnt = nullptr;
+    // real-space neighbour lists, one segment per class pair
+    int *d_nbr_bra = nullptr, *d_nbr_ket = nullptr;
+    long nbr_off[22] = {0};
     int gchunk = 0;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     // event pairs around GEMM and structure-factor launches of one build
@@ -87,7 +90,8 @@ void release(pbc_jk *h)
     void *ptrs[] = {h->d_pairs, h->d_groups, h->d_boys, h->d_S, h->d_G, h->d_Gw, h->d_sp_start, h->d_sp_pairs,
                     h->d_sp_shA, h->d_sp_shB, h->d_sh_l, h->d_sh_aoc, h->d_tr_ao, h->d_inv_ci, h->d_tr_c,
                     h->d_dscale, h->d_inv_cc, h->d_D, h->d_Dt, h->d_Dmax, h->d_X, h->d_Y, h->d_Jt, h->d_Kt,
-                    h->d_F, h->d_T, h->d_rho, h->d_scal, h->d_Jo, h->d_Ko, h->d_dmaxg, h->d_cnt};
+                    h->d_F, h->d_T, h->d_rho, h->d_scal, h->d_Jo, h->d_Ko, h->d_dmaxg, h->d_cnt,
+                    h->d_nbr_bra, h->d_nbr_ket};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &e : h->ev)
@@ -116,6 +120,8 @@ struct TimedLaunch {
         if (slot >= 0) (void)hipEventRecord(h->tev[2 * slot + 1], st);
     }
 };
+
+int build_neighbours(pbc_jk *h);
 
 int create_device(pbc_jk *h)
 {
@@ -171,7 +177,7 @@ int create_device(pbc_jk *h)
     if ((rc = dalloc(&h->d_Ko, m2))) return rc;
     if ((rc = dalloc(&h->d_scal, 4))) return rc;
     if ((rc = dalloc(&h->d_dmaxg, 1))) return rc;
-    if ((rc = dalloc(&h->d_cnt, 4))) return rc;
+    if ((rc = dalloc(&h->d_cnt, 32))) return rc;
     // reciprocal-space chunk: F and T hold 2 * gchunk matrices each
     const int nG = (int)S.Gw.size();
     double budget_mb = 16384.0;
@@ -181,6 +187,74 @@ int create_device(pbc_jk *h)
     if ((rc = dalloc(&h->d_F, 2 * (size_t)h->gchunk * n2))) return rc;
     if ((rc = dalloc(&h->d_T, std::max<size_t>(2 * (size_t)h->gchunk * n2, n2)))) return rc;
     if ((rc = dalloc(&h->d_rho, 2 * (size_t)h->gchunk))) return rc;
+    return build_neighbours(h);
+}
+
+LatArgs lat_args(const Setup &S)
+{
+    LatArgs l;
+    std::memcpy(l.M, S.lat.M, sizeof l.M);
+    std::memcpy(l.Minv, S.lat.Minv, sizeof l.Minv);
+    std::memcpy(l.span, S.lat.span, sizeof l.span);
+    l.Rmin = S.lat.Rmin;
+    return l;
+}
+
+// Real-space neighbour lists of every class pair: count, scan on the host,
+// fill in bra order.
+int build_neighbours(pbc_jk *h)
+{
+    const Setup &S = h->S;
+    hipStream_t st = h->own;
+    NbrArgs a{};
+    a.pairs = h->d_pairs; a.groups = h->d_groups; a.lat = lat_args(S);
+    a.w2 = S.omega * S.omega; a.d_ewald_R = S.d_ewald_R; a.rcap2 = S.r_cut > 0 ? S.r_cut * S.r_cut : 0.0;
+    int maxnb = 0;
+    for (int c = 0; c < kNumClass; ++c) maxnb = std::max(maxnb, S.class_start[c + 1] - S.class_start[c]);
+    int *d_counts = nullptr;
+    long *d_offs = nullptr;
+    int rc;
+    if ((rc = dalloc(&d_counts, std::max(1, maxnb)))) return rc;
+    if ((rc = dalloc(&d_offs, std::max(1, maxnb)))) { (void)hipFree(d_counts); return rc; }
+    std::vector<std::vector<long>> offs(21);
+    std::vector<int> cnt(std::max(1, maxnb));
+    long total = 0;
+    int slot = 0;
+    for (int cb = 0; cb < kNumClass; ++cb)
+        for (int ck = cb; ck < kNumClass; ++ck, ++slot) {
+            h->nbr_off[slot] = total;
+            a.gb0 = S.class_start[cb]; a.nb = S.class_start[cb + 1] - S.class_start[cb];
+            a.gk0 = S.class_start[ck]; a.nk = S.class_start[ck + 1] - S.class_start[ck];
+            a.tri = (cb == ck);
+            if (a.nb == 0 || a.nk == 0) continue;
+            a.mode = 0; a.counts = d_counts;
+            HIPCHK(launch_nbr(a, st));
+            HIPCHK(hipMemcpyAsync(cnt.data(), d_counts, a.nb * sizeof(int), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            offs[slot].resize(a.nb);
+            for (int i = 0; i < a.nb; ++i) { offs[slot][i] = total; total += cnt[i]; }
+        }
+    h->nbr_off[21] = total;
+    if ((rc = dalloc(&h->d_nbr_bra, (size_t)std::max(1L, total))) ||
+        (rc = dalloc(&h->d_nbr_ket, (size_t)std::max(1L, total)))) {
+        (void)hipFree(d_counts); (void)hipFree(d_offs);
+        return rc;
+    }
+    slot = 0;
+    for (int cb = 0; cb < kNumClass; ++cb)
+        for (int ck = cb; ck < kNumClass; ++ck, ++slot) {
+            a.gb0 = S.class_start[cb]; a.nb = S.class_start[cb + 1] - S.class_start[cb];
+            a.gk0 = S.class_start[ck]; a.nk = S.class_start[ck + 1] - S.class_start[ck];
+            a.tri = (cb == ck);
+            if (a.nb == 0 || a.nk == 0 || h->nbr_off[slot + 1] == h->nbr_off[slot]) continue;
+            HIPCHK(hipMemcpyAsync(d_offs, offs[slot].data(), a.nb * sizeof(long), hipMemcpyHostToDevice, st));
+            a.mode = 1; a.offsets = d_offs; a.out_bra = h->d_nbr_bra; a.out_ket = h->d_nbr_ket;
+            HIPCHK(launch_nbr(a, st));
+            HIPCHK(hipStreamSynchronize(st));
+        }
+    (void)hipFree(d_counts);
+    (void)hipFree(d_offs);
+    h->st.n_group_pairs = (double)total;
     return 0;
 }
 
@@ -204,26 +278,29 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
     HIPCHK(launch_fill(h->d_Y, n2, 0.0, st));
     HIPCHK(launch_fill(h->d_Jt, n2, 0.0, st));
     HIPCHK(launch_fill(h->d_Kt, n2, 0.0, st));
-    HIPCHK(launch_fill((double *)h->d_cnt, 4, 0.0, st));
+    HIPCHK(launch_fill((double *)h->d_cnt, 32, 0.0, st));
 
     // B3/B4: short-range J and K
     if (h->parts & PBC_JK_PART_SR) {
         SRArgs a{};
         a.pairs = h->d_pairs; a.groups = h->d_groups;
-        a.Dt = h->d_Dt; a.Dmax = h->d_Dmax; a.dmax_glob = (const double *)h->d_dmaxg;
+        a.Dt = h->d_Dt; a.Dmax = h->d_Dmax;
         a.X = h->d_X; a.Y = h->d_Y; a.nbfc = n; a.nshell = S.nshell;
-        std::memcpy(a.M, S.lat.M, sizeof a.M);
-        std::memcpy(a.Minv, S.lat.Minv, sizeof a.Minv);
-        std::memcpy(a.span, S.lat.span, sizeof a.span);
+        a.lat = lat_args(S);
         a.w2 = S.omega * S.omega; a.d_schwarz = S.d_schwarz; a.d_ewald_R = S.d_ewald_R;
         a.rcap2 = S.r_cut > 0 ? S.r_cut * S.r_cut : 0.0;
+        a.fp32_below = S.fp32_below;
         a.boys = h->d_boys; a.counters = h->d_cnt;
+        int slot = 0;
         for (int cb = 0; cb < kNumClass; ++cb)
-            for (int ck = cb; ck < kNumClass; ++ck) {
-                a.gb0 = S.class_start[cb]; a.nb = S.class_start[cb + 1] - S.class_start[cb];
-                a.gk0 = S.class_start[ck]; a.nk = S.class_start[ck + 1] - S.class_start[ck];
+            for (int ck = cb; ck < kNumClass; ++ck, ++slot) {
+                a.slot = slot;
+                a.gb0 = S.class_start[cb];
+                a.gk0 = S.class_start[ck];
                 a.tri = (cb == ck);
-                if (a.nb == 0 || a.nk == 0) continue;
+                const long e0 = h->nbr_off[slot], e1 = h->nbr_off[slot + 1];
+                a.nbr_bra = h->d_nbr_bra + e0; a.nbr_ket = h->d_nbr_ket + e0; a.n_entries = e1 - e0;
+                if (a.n_entries == 0) continue;
                 hipError_t e = launch_sr_jk(cb, ck, a, st);
                 if (e == hipErrorNotSupported) return fail(PBC_JK_ENOTSUP, "d-shell kernels not built");
                 HIPCHK(e);
@@ -375,10 +452,6 @@ int pbc_jk_create(const pbc_cell *cell, const pbc_atoms *atoms, const pbc_basis 
             return fail(PBC_JK_ENOTSUP, "d shells are not supported by this build");
         }
 #endif
-    if (h->S.fp32_below > 0) {
-        delete h;
-        return fail(PBC_JK_ENOTSUP, "mixed precision (fp32_below > 0) is not available in this build");
-    }
     rc = create_device(h);
     if (rc) {
         std::string keep = g_err;
@@ -474,10 +547,12 @@ int pbc_jk_stats(const pbc_jk *hc, pbc_jk_counters *out)
         HIPCHK(hipEventElapsedTime(&b, h->ev[1], h->ev[2]));
         HIPCHK(hipEventElapsedTime(&c, h->ev[2], h->ev[3]));
         h->st.t_sr_ms = a; h->st.t_lr_ms = b; h->st.t_other_ms = c;
-        unsigned long long cnt[2];
+        unsigned long long cnt[2 + 21 + 1];
         HIPCHK(hipMemcpy(cnt, h->d_cnt, sizeof cnt, hipMemcpyDeviceToHost));
         h->st.quartets = (double)cnt[0];
         h->st.terms = (double)cnt[1];
+        h->st.terms_fp32 = (double)cnt[23];
+        for (int k = 0; k < 21; ++k) h->st.terms_class[k] = (double)cnt[2 + k];
         h->st.t_gemm_ms = h->st.t_sfac_ms = h->st.gemm_flops = 0.0;
         h->st.n_gemm = 0;
         for (int i = 0; i < h->ntimed; ++i) {

@@ -57,11 +57,10 @@ __device__ __forceinline__ void herm_axis(double h, double xa, double xb, EAxis<
 }
 
 // R_{tuv} = R^0_{tuv} for t+u+v <= L from R^m_{000}, m = 0..L.
-template <int L>
-__device__ __forceinline__ void herm_R(const double (&R0)[L + 1], double X, double Y, double Z,
-                                       double (&R)[L + 1][L + 1][L + 1])
+template <int L, typename V>
+__device__ __forceinline__ void herm_R(const V (&R0)[L + 1], V X, V Y, V Z, V (&R)[L + 1][L + 1][L + 1])
 {
-    double T[L + 1][L + 1][L + 1][L + 1];
+    V T[L + 1][L + 1][L + 1][L + 1];
 #pragma unroll
     for (int n = L; n >= 0; --n)
 #pragma unroll
@@ -70,11 +69,11 @@ __device__ __forceinline__ void herm_R(const double (&R0)[L + 1], double X, doub
             for (int u = 0; u <= L - n - t; ++u)
 #pragma unroll
                 for (int v = 0; v <= L - n - t - u; ++v) {
-                    double r;
+                    V r;
                     if (t == 0 && u == 0 && v == 0) r = R0[n];
-                    else if (t > 0) r = (t >= 2 ? (t - 1) * T[n + 1][t - 2][u][v] : 0.0) + X * T[n + 1][t - 1][u][v];
-                    else if (u > 0) r = (u >= 2 ? (u - 1) * T[n + 1][0][u - 2][v] : 0.0) + Y * T[n + 1][0][u - 1][v];
-                    else r = (v >= 2 ? (v - 1) * T[n + 1][0][0][v - 2] : 0.0) + Z * T[n + 1][0][0][v - 1];
+                    else if (t > 0) r = (t >= 2 ? V(t - 1) * T[n + 1][t - 2][u][v] : V(0)) + X * T[n + 1][t - 1][u][v];
+                    else if (u > 0) r = (u >= 2 ? V(u - 1) * T[n + 1][0][u - 2][v] : V(0)) + Y * T[n + 1][0][u - 1][v];
+                    else r = (v >= 2 ? V(v - 1) * T[n + 1][0][0][v - 2] : V(0)) + Z * T[n + 1][0][0][v - 1];
                     T[n][t][u][v] = r;
                 }
 #pragma unroll
@@ -137,6 +136,127 @@ __device__ __forceinline__ void sr_R0(double rho, double w2, double T, const dou
         f1 *= -2.0 * rho;
         f2 *= -2.0 * ap;
     }
+}
+
+// FP32 F_m(T) from the same table (six Taylor terms suffice in single
+// precision); the offset from the grid point is formed in FP64.
+template <int L>
+__device__ __forceinline__ void boys_f32(double Td, const double *__restrict__ tab, float (&F)[L + 1])
+{
+    const float T = (float)Td;
+    if (Td < kBoysTmax) {
+        int k = __double2int_rn(Td * (1.0 / kBoysStep));
+        float x = (float)(k * kBoysStep - Td);
+        const double *r = tab + k * kBoysTerms;
+        float s = (float)r[5];
+#pragma unroll
+        for (int j = 4; j >= 0; --j) s = (float)r[j] + s * x * (1.0f / (j + 1));
+        F[L] = s;
+        if (L > 0) {
+            float e = __expf(-T);
+#pragma unroll
+            for (int m = L - 1; m >= 0; --m) F[m] = (2.0f * T * F[m + 1] + e) * (1.0f / (2 * m + 1));
+        }
+    } else {
+        float it = 1.0f / T;
+        F[0] = 0.88622692545f * sqrtf(it);
+        if (L > 0) {
+            float e = __expf(-T);
+#pragma unroll
+            for (int m = 0; m < L; ++m) F[m + 1] = ((2 * m + 1) * F[m] - e) * (0.5f * it);
+        }
+    }
+}
+
+// Short-range R^m_{000} in FP32 for a low-bound quartet.  Small arguments
+// (rho T < 1: both Boys arguments in the Taylor region, where the
+// difference 1 - c ... cancels) are evaluated in FP64 and rounded.
+template <int L>
+__device__ __forceinline__ void sr_R0_mixed(double rho, double w2, double T, const double *__restrict__ tab,
+                                            float (&R0)[L + 1])
+{
+    if (rho * T < 1.0) {
+        double R0d[L + 1];
+        sr_R0<L>(rho, w2, T, tab, R0d);
+#pragma unroll
+        for (int m = 0; m <= L; ++m) R0[m] = (float)R0d[m];
+        return;
+    }
+    const double den = 1.0 / (rho + w2);
+    const double ap = rho * w2 * den;
+    float F1[L + 1], F2[L + 1];
+    boys_f32<L>(rho * T, tab, F1);
+    boys_f32<L>(ap * T, tab, F2);
+    float f1 = 1.0f, f2 = (float)sqrt(w2 * den);
+    const float r2 = (float)(-2.0 * rho), a2 = (float)(-2.0 * ap);
+#pragma unroll
+    for (int m = 0; m <= L; ++m) {
+        R0[m] = f1 * F1[m] - f2 * F2[m];
+        f1 *= r2;
+        f2 *= a2;
+    }
+}
+
+constexpr double kTwoPi52 = 34.98683665524972497;   // 2 pi^{5/2}
+
+// Real-space sphere of one primitive quartet (Sec. 2.4, eq.
+// pbc_eri_real_cutoff_implementation): false when C2e (1 - c) <= delta, else
+// rad2 = (1/p + 1/q + 1/w^2) ln(C2e (1 - c)/delta).  Shared by the
+// neighbour-list builder and the build kernels so that both take the same
+// decisions.
+__device__ __forceinline__ bool quartet_sphere(const PairRec &b, const PairRec &k, double w2, double dR,
+                                               double &rad2)
+{
+    const double p = b.p, q = k.p, pq = p * q;
+    const double rho = pq / (p + q);
+    const double c = sqrt(w2 / (rho + w2));
+    const double C2e = b.Cb * k.Cb * kTwoPi52 / (pq * sqrt(p + q));
+    const double arg = C2e * (1.0 - c) / dR;
+    if (!(arg > 1.0)) return false;
+    rad2 = (1.0 / p + 1.0 / q + 1.0 / w2) * log(arg);
+    return true;
+}
+
+__device__ __forceinline__ void lat_image(const LatArgs &lat, const double cen[3], int n0, int n1, int n2,
+                                          double L[3])
+{
+#pragma unroll
+    for (int x = 0; x < 3; ++x) L[x] = cen[x] - (n0 * lat.M[x] + n1 * lat.M[3 + x] + n2 * lat.M[6 + x]);
+}
+
+// Calls f(L) for every lattice translate L = cen - R1 with |L|^2 < rad2 (and
+// |L|^2 <= rcap2 when rcap2 > 0).  Fast path: when sqrt(rad2) <= Rmin - |L0|
+// for the rounded image L0, no other translate can lie inside the sphere.
+template <class F>
+__device__ __forceinline__ void for_images(const LatArgs &lat, const double cen[3], double rad2, double rcap2,
+                                           F &&f)
+{
+    double fr[3];
+#pragma unroll
+    for (int x = 0; x < 3; ++x) fr[x] = cen[0] * lat.Minv[x] + cen[1] * lat.Minv[3 + x] + cen[2] * lat.Minv[6 + x];
+    double L[3];
+    lat_image(lat, cen, (int)rint(fr[0]), (int)rint(fr[1]), (int)rint(fr[2]), L);
+    const double L2 = L[0] * L[0] + L[1] * L[1] + L[2] * L[2];
+    const double rad = sqrt(rad2);
+    if (rad <= lat.Rmin - sqrt(L2)) {
+        if (L2 < rad2 && !(rcap2 > 0 && L2 > rcap2)) f(L, L2);
+        return;
+    }
+    const double r = rad * (1.0 + 1e-9) + 1e-9;
+    int lo[3], hi[3];
+#pragma unroll
+    for (int x = 0; x < 3; ++x) {
+        lo[x] = (int)floor(fr[x] - r * lat.span[x]);
+        hi[x] = (int)ceil(fr[x] + r * lat.span[x]);
+    }
+    for (int n0 = lo[0]; n0 <= hi[0]; ++n0)
+        for (int n1 = lo[1]; n1 <= hi[1]; ++n1)
+            for (int n2 = lo[2]; n2 <= hi[2]; ++n2) {
+                double Lb[3];
+                lat_image(lat, cen, n0, n1, n2, Lb);
+                const double Lb2 = Lb[0] * Lb[0] + Lb[1] * Lb[1] + Lb[2] * Lb[2];
+                if (Lb2 < rad2 && !(rcap2 > 0 && Lb2 > rcap2)) f(Lb, Lb2);
+            }
 }
 
 }  // namespace pbcjk

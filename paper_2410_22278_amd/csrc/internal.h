@@ -42,7 +42,10 @@ struct GroupRec {
     int aoA, aoB;       // first scaled-Cartesian AO of each shell
     int pstart, pend;   // range in the pair array
     double Qmax;        // max Q over the group's pairs
-    double pad;
+    double C[3];        // centre: P of the group's first pair
+    double ext;         // max |P - C| over the group's pairs
+    double Zmax;        // max Z (separable real-space bound, see setup.cpp)
+    double pmin;        // min p over the group's pairs
 };
 
 struct Lattice {
@@ -51,6 +54,13 @@ struct Lattice {
     double span[3];    // sum_i |Minv[i][j]|
     double V;
     double B[9];       // reciprocal rows, a_i . b_j = 2 pi delta_ij
+    double Rmin;       // lower bound on the shortest non-zero lattice vector
+};
+
+// Lattice data passed by value to kernels.
+struct LatArgs {
+    double M[9], Minv[9], span[3];
+    double Rmin;
 };
 
 // Host-side description built once per handle.

@@ -9,19 +9,39 @@ namespace pbcjk {
 struct SRArgs {
     const PairRec *pairs;
     const GroupRec *groups;
-    int gb0, nb;          // bra class: group range [gb0, gb0 + nb)
-    int gk0, nk;          // ket class: group range [gk0, gk0 + nk)
-    int tri;              // same class: only ket index >= bra index
+    int gb0, gk0;         // first group of the bra and ket classes
+    int tri;              // same class: the diagonal group pair has weight 1/2
+    const int *nbr_bra;   // neighbour list of this class pair (bra, ket indices
+    const int *nbr_ket;   //   within their classes), n_entries long
+    long n_entries;
     const double *Dt;     // scaled Cartesian density, nbfc x nbfc
     const double *Dmax;   // nshell x nshell block maxima of the Cartesian density
-    const double *dmax_glob;
     double *X, *Y;        // J and K halves, nbfc x nbfc
     int nbfc, nshell;
-    double M[9], Minv[9], span[3];
+    LatArgs lat;
     double w2, d_schwarz, d_ewald_R, rcap2;
+    double fp32_below;    // > 0: quartets with Q Q w_D below it are evaluated in FP32
     const double *boys;   // kBoysNT x kBoysM
-    unsigned long long *counters;   // [0] primitive quartets, [1] (quartet, R1) terms
+    unsigned long long *counters;   // [0] primitive quartets, [1] (quartet, R1) terms,
+                                    // [2 + slot] terms of this class pair, [23] FP32 terms
+    int slot;             // class-pair index (0..20)
 };
+
+// Neighbour list of one class pair: every (bra group, ket group) that has at
+// least one real-space term for some density (mode 0 counts per bra, mode 1
+// writes the ket indices at the given per-bra offsets, in ket order).
+struct NbrArgs {
+    const PairRec *pairs;
+    const GroupRec *groups;
+    int gb0, nb, gk0, nk, tri;
+    LatArgs lat;
+    double w2, d_ewald_R, rcap2;
+    int mode;
+    int *counts;          // nb
+    const long *offsets;  // nb
+    int *out_bra, *out_ket;
+};
+hipError_t launch_nbr(const NbrArgs &a, hipStream_t st);
 
 hipError_t launch_sr_jk(int cb, int ck, const SRArgs &a, hipStream_t st);
 

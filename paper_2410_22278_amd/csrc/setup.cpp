@@ -57,6 +57,13 @@ void lattice_setup(const double *cell, Lattice &L)
         L.span[j] = std::fabs(L.Minv[j]) + std::fabs(L.Minv[3 + j]) + std::fabs(L.Minv[6 + j]);
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) L.B[3 * i + j] = 2.0 * kPi * L.Minv[3 * j + i];
+    // any non-zero lattice vector has some index n_i != 0 and is then at least
+    // one interplanar spacing 1/|Minv[:, i]| long
+    L.Rmin = 1e300;
+    for (int j = 0; j < 3; ++j) {
+        double c2 = L.Minv[j] * L.Minv[j] + L.Minv[3 + j] * L.Minv[3 + j] + L.Minv[6 + j] * L.Minv[6 + j];
+        L.Rmin = std::min(L.Rmin, 1.0 / std::sqrt(c2));
+    }
 }
 
 void to_frac(const double *Minv, const double x[3], double f[3])
@@ -234,7 +241,7 @@ int build_setup(const double *cell, int natom, const double *xyz, int nshell, co
     }
 
     // ---------------- unique local primitive pairs
-    struct Tmp { int cls, first, second, n0, n1, n2; PairRec rec; };
+    struct Tmp { int cls, first, second, n0, n1, n2; PairRec rec; double Z; };
     std::vector<Tmp> tmp;
     const Lattice &L = S.lat;
     const double rcap2 = S.r_cut > 0 ? S.r_cut * S.r_cut : 0.0;
@@ -297,6 +304,11 @@ int build_setup(const double *cell, int natom, const double *xyz, int nshell, co
                         t.rec.Q = Y0 * g;
                         t.rec.Cb = Cab * g;
                         t.rec.pad[0] = t.rec.pad[1] = t.rec.pad[2] = 0.0;
+                        // Separable real-space bound: C2e (1 - c) <= Z_bra Z_ket, using
+                        // 2pi^{5/2}/(pq sqrt(p+q)) <= prod sqrt2 pi^{5/4}/(p (p+2amin)^{1/4})
+                        // and 1 - w/sqrt(rho+w^2) <= sqrt(prod (1 - w/sqrt(p+w^2))).
+                        t.Z = std::sqrt(2.0) * std::pow(kPi, 1.25) * Cab * g / (p * std::pow(p + 2.0 * S.amin, 0.25)) *
+                              std::sqrt(1.0 - S.omega / std::sqrt(p + S.omega * S.omega));
                         tmp.push_back(t);
                     });
                 }
@@ -312,22 +324,28 @@ int build_setup(const double *cell, int natom, const double *xyz, int nshell, co
         if (kx != ky) return kx < ky;
         return tmp[x].rec.Q > tmp[y].rec.Q;
     });
-    struct G0 { size_t b, e; double qmax; int cls; };
+    struct G0 { size_t b, e; double qmax, zmax, pmin; int cls; };
     std::vector<G0> gl;
     for (size_t k = 0; k < idx.size();) {
         size_t e = k;
-        double qm = 0;
+        double qm = 0, zm = 0, pm = 1e300;
         while (e < idx.size() && gkey(tmp[idx[e]]) == gkey(tmp[idx[k]])) {
             qm = std::max(qm, tmp[idx[e]].rec.Q);
+            zm = std::max(zm, tmp[idx[e]].Z);
+            pm = std::min(pm, tmp[idx[e]].rec.p);
             ++e;
         }
-        gl.push_back({k, e, qm, tmp[idx[k]].cls});
+        gl.push_back({k, e, qm, zm, pm, tmp[idx[k]].cls});
         k = e;
     }
+    // within a class: more primitive pairs first (similar loop lengths on
+    // neighbouring lanes), then descending Cauchy-Schwarz value
     std::vector<size_t> gord(gl.size());
     std::iota(gord.begin(), gord.end(), 0);
     std::stable_sort(gord.begin(), gord.end(), [&](size_t x, size_t y) {
         if (gl[x].cls != gl[y].cls) return gl[x].cls < gl[y].cls;
+        size_t nx = gl[x].e - gl[x].b, ny = gl[y].e - gl[y].b;
+        if (nx != ny) return nx > ny;
         return gl[x].qmax > gl[y].qmax;
     });
     S.pairs.clear(); S.groups.clear();
@@ -342,7 +360,15 @@ int build_setup(const double *cell, int natom, const double *xyz, int nshell, co
         G.pstart = (int)S.pairs.size();
         for (size_t k = g.b; k < g.e; ++k) S.pairs.push_back(tmp[idx[k]].rec);
         G.pend = (int)S.pairs.size();
-        G.Qmax = g.qmax; G.pad = 0.0;
+        G.Qmax = g.qmax; G.Zmax = g.zmax; G.pmin = g.pmin;
+        const PairRec &P0 = S.pairs[G.pstart];
+        G.C[0] = P0.P[0]; G.C[1] = P0.P[1]; G.C[2] = P0.P[2];
+        G.ext = 0.0;
+        for (int k = G.pstart; k < G.pend; ++k) {
+            const PairRec &Pk = S.pairs[k];
+            double dx = Pk.P[0] - G.C[0], dy = Pk.P[1] - G.C[1], dz = Pk.P[2] - G.C[2];
+            G.ext = std::max(G.ext, std::sqrt(dx * dx + dy * dy + dz * dz));
+        }
         S.groups.push_back(G);
         S.class_start[g.cls + 1]++;
     }

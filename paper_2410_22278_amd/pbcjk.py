@@ -53,7 +53,8 @@ class pbc_jk_counters(ctypes.Structure):
                 ("terms", c_double), ("terms_fp32", c_double), ("t_setup_ms", c_double),
                 ("t_build_ms", c_double), ("t_sr_ms", c_double), ("t_lr_ms", c_double),
                 ("t_other_ms", c_double), ("t_gemm_ms", c_double), ("gemm_flops", c_double),
-                ("n_gemm", c_int), ("t_sfac_ms", c_double)]
+                ("n_gemm", c_int), ("t_sfac_ms", c_double), ("terms_class", c_double * 21),
+                ("n_group_pairs", c_double)]
 
 
 class PbcJkError(RuntimeError):
@@ -185,7 +186,9 @@ def pbc_jk_nbf(h: int) -> int:
 def pbc_jk_stats(h: int) -> dict:
     s = pbc_jk_counters()
     _check(load().pbc_jk_stats(c_void_p(h), byref(s)))
-    return {k: getattr(s, k) for k, _ in s._fields_}
+    out = {k: getattr(s, k) for k, _ in s._fields_}
+    out["terms_class"] = list(s.terms_class)
+    return out
 
 
 def pbc_jk_set_parts(h: int, mask: int):

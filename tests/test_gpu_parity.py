@@ -131,3 +131,42 @@ def test_cfg2_sampled_rows(lib, oracle_mod):
     assert dJ < 1e-9 and dK < 1e-9
     assert np.abs(J - J.T).max() < 1e-12 and np.abs(K - K.T).max() < 1e-12
     assert EJ > 0 and EK < 0
+
+
+MIXED = [
+    dict(seed=5, natom=3, recipe=((0, 0), (0, 0), (1, 0)), skew=0.15, omega=0.35),
+    dict(seed=13, natom=4, recipe=((0, 0), (1, 0)), nprim=3, a_ang=3.5, omega=0.8),
+]
+
+
+@pytest.mark.parametrize("case", MIXED, ids=["mixed5", "mixed13"])
+def test_mixed_precision_small(lib, oracle_mod, case):
+    """FP32 for every quartet whose density-weighted bound is below 1e-2
+    (most of them, to exercise the single-precision path) against the FP64
+    oracle: stated tolerances 1e-7 for matrix elements, 1e-6 Eh/atom."""
+    s = inputs.small_cell(**case)
+    ref = oracle_mod.jk(s)
+    thr = Thresholds(**{**s.thr.__dict__, "fp32_below": 1e-2})
+    with lib.Handle(s, thr=thr) as h:
+        J, K, EJ, EK = h.build(s.D)
+        st = h.stats()
+    dJ, dK, dEJ, dEK = _report(f"mixed {s.name} (fp32 terms {st['terms_fp32']:.0f}/{st['terms']:.0f})",
+                               J, K, ref, s.natom, EJ, EK)
+    assert st["terms_fp32"] > 0
+    assert dJ < 1e-7 and dK < 1e-7 and dEJ < 1e-6 and dEK < 1e-6
+
+
+def test_cfg3_mixed_sampled_rows(lib, oracle_mod):
+    """The 64-water cell in mixed precision (FP32 below a bound of 1e-6)
+    against the FP64 oracle's exact rows of three bra shells."""
+    s = inputs.cfg3()
+    shells = [0, 3, 7]
+    ref = oracle_mod.jk(s, bra_shells=shells)
+    with lib.Handle(s) as h:
+        J, K, EJ, EK = h.build(s.D)
+        st = h.stats()
+    print(f"cfg3: fp32 terms {st['terms_fp32']:.3e} of {st['terms']:.3e}; build {st['t_build_ms']:.1f} ms "
+          f"(sr {st['t_sr_ms']:.1f})", flush=True)
+    dJ, dK, _, _ = _report("cfg3 rows", J, K, ref, s.natom)
+    assert st["terms_fp32"] > 0
+    assert dJ < 1e-7 and dK < 1e-7
