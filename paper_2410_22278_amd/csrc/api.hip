@@ -16,6 +16,8 @@ using namespace pbcjk;
 
 namespace {
 
+constexpr int kClassL[kNumClass] = {0, 1, 2, 2, 3, 4};
+
 thread_local std::string g_err;
 
 int fail(int code, const std::string &msg)
@@ -301,7 +303,9 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
                 const long e0 = h->nbr_off[slot], e1 = h->nbr_off[slot + 1];
                 a.nbr_bra = h->d_nbr_bra + e0; a.nbr_ket = h->d_nbr_ket + e0; a.n_entries = e1 - e0;
                 if (a.n_entries == 0) continue;
-                hipError_t e = launch_sr_jk(cb, ck, a, st);
+                // class pairs with a d shell and L >= 4 use one wavefront per group pair
+                const bool coop = (kClassL[cb] + kClassL[ck] >= 4) && (cb >= 3 || ck >= 3);
+                hipError_t e = coop ? launch_sr_coop(cb, ck, a, st) : launch_sr_jk(cb, ck, a, st);
                 if (e == hipErrorNotSupported) return fail(PBC_JK_ENOTSUP, "d-shell kernels not built");
                 HIPCHK(e);
             }
@@ -314,14 +318,18 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
         SfacArgs sa{};
         sa.pairs = h->d_pairs; sa.sp_start = h->d_sp_start; sa.sp_pairs = h->d_sp_pairs;
         sa.sp_shA = h->d_sp_shA; sa.sp_shB = h->d_sp_shB; sa.sh_l = h->d_sh_l; sa.sh_aoc = h->d_sh_aoc;
-        sa.nsp = (int)S.sp_shA.size(); sa.F = h->d_F; sa.nbfc = n;
+        sa.F = h->d_F; sa.nbfc = n;
         for (int g0 = 0; g0 < nG; g0 += h->gchunk) {
             const int gc = std::min(h->gchunk, nG - g0);
             HIPCHK(launch_fill(h->d_F, 2L * gc * n2, 0.0, st));
             sa.G = h->d_G + 3 * g0; sa.ng = gc;
             {
                 TimedLaunch tl(h, st, 1, 0.0);
-                HIPCHK(launch_sfac(sa, st));
+                for (int c = 0; c < kNumClass; ++c) {
+                    sa.sp0 = S.sp_class_start[c];
+                    sa.nsp = S.sp_class_start[c + 1] - S.sp_class_start[c];
+                    HIPCHK(launch_sfac(c, sa, st));
+                }
             }
             if (wantJ) {
                 HIPCHK(launch_dot_batched(h->d_F, h->d_Dt, (int)n2, 2 * gc, h->d_rho, st));

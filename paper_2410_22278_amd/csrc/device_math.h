@@ -88,13 +88,13 @@ __device__ __forceinline__ void herm_R(const V (&R0)[L + 1], V X, V Y, V Z, V (&
 // layout [k][j].  Below kBoysTmax: Taylor expansion of F_L about the
 // nearest grid point, then downward recursion; above: asymptotic F_0 and
 // upward recursion.
-template <int L>
+template <int L, int STRIDE = kBoysTerms>
 __device__ __forceinline__ void boys_f64(double T, const double *__restrict__ tab, double (&F)[L + 1])
 {
     if (T < kBoysTmax) {
         int k = __double2int_rn(T * (1.0 / kBoysStep));
         double x = k * kBoysStep - T;
-        const double *r = tab + k * kBoysTerms;
+        const double *r = tab + k * STRIDE;
         double s = r[kBoysTerms - 1];
 #pragma unroll
         for (int j = kBoysTerms - 2; j >= 0; --j) s = r[j] + s * x * (1.0 / (j + 1));
@@ -119,7 +119,7 @@ __device__ __forceinline__ void boys_f64(double T, const double *__restrict__ ta
 // T = |L|^2 (Sec. 2.3 Boys split):
 //   (-2 rho)^m F_m(rho T) - c (-2 a')^m F_m(a' T),
 //   a' = rho w^2/(rho + w^2), c = w/sqrt(rho + w^2).
-template <int L>
+template <int L, int STRIDE = kBoysTerms>
 __device__ __forceinline__ void sr_R0(double rho, double w2, double T, const double *__restrict__ tab,
                                       double (&R0)[L + 1])
 {
@@ -127,8 +127,8 @@ __device__ __forceinline__ void sr_R0(double rho, double w2, double T, const dou
     double ap = rho * w2 * den;
     double c = sqrt(w2 * den);
     double F1[L + 1], F2[L + 1];
-    boys_f64<L>(rho * T, tab, F1);
-    boys_f64<L>(ap * T, tab, F2);
+    boys_f64<L, STRIDE>(rho * T, tab, F1);
+    boys_f64<L, STRIDE>(ap * T, tab, F2);
     double f1 = 1.0, f2 = c;
 #pragma unroll
     for (int m = 0; m <= L; ++m) {

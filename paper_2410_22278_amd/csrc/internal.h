@@ -88,6 +88,7 @@ struct Setup {
     std::vector<int> sp_start;      // unique shell pairs: ranges into sp_pairs
     std::vector<int> sp_pairs;      // pair indices grouped by shell pair
     std::vector<int> sp_shA, sp_shB;
+    int sp_class_start[kNumClass + 1] = {0};   // shell pairs sorted by class
     long n_pairs_ordered = 0;
 };
 

@@ -44,6 +44,8 @@ struct NbrArgs {
 hipError_t launch_nbr(const NbrArgs &a, hipStream_t st);
 
 hipError_t launch_sr_jk(int cb, int ck, const SRArgs &a, hipStream_t st);
+// class pairs with total angular momentum >= 5 (one wavefront per group pair)
+hipError_t launch_sr_coop(int cb, int ck, const SRArgs &a, hipStream_t st);
 
 // ---- long range and utilities (lr.hip)
 
@@ -53,13 +55,13 @@ struct SfacArgs {
     const PairRec *pairs;
     const int *sp_start, *sp_pairs, *sp_shA, *sp_shB;
     const int *sh_l, *sh_aoc;
-    int nsp;
+    int sp0, nsp;         // shell-pair range of one class
     const double *G;      // 3 * ng
     int ng;
     double *F;            // 2 ng x nbfc x nbfc
     int nbfc;
 };
-hipError_t launch_sfac(const SfacArgs &a, hipStream_t st);
+hipError_t launch_sfac(int cls, const SfacArgs &a, hipStream_t st);
 
 // rho[b] = sum_{mu nu} Dt[mu nu] F[b][mu nu] for b < nb.
 hipError_t launch_dot_batched(const double *F, const double *Dt, int n2, int nb, double *rho, hipStream_t st);

@@ -115,22 +115,15 @@ __device__ __forceinline__ void sfac_store(const SfacArgs &a, int sp, int g, dou
     }
 }
 
-// one block per shell pair, threads over reciprocal vectors
+// one block per shell pair of one class, threads over reciprocal vectors
+template <int LA, int LB>
 __global__ __launch_bounds__(64) void k_sfac(SfacArgs a)
 {
-    const int sp = blockIdx.y;
+    const int sp = a.sp0 + blockIdx.y;
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= a.ng) return;
     const double Gx = a.G[3 * g], Gy = a.G[3 * g + 1], Gz = a.G[3 * g + 2];
-    const int la = a.sh_l[a.sp_shA[sp]], lb = a.sh_l[a.sp_shB[sp]];
-    switch (class_of(la, lb)) {
-        case 0: sfac_store<0, 0>(a, sp, g, Gx, Gy, Gz); break;
-        case 1: sfac_store<1, 0>(a, sp, g, Gx, Gy, Gz); break;
-        case 2: sfac_store<1, 1>(a, sp, g, Gx, Gy, Gz); break;
-        case 3: sfac_store<2, 0>(a, sp, g, Gx, Gy, Gz); break;
-        case 4: sfac_store<2, 1>(a, sp, g, Gx, Gy, Gz); break;
-        default: sfac_store<2, 2>(a, sp, g, Gx, Gy, Gz); break;
-    }
+    sfac_store<LA, LB>(a, sp, g, Gx, Gy, Gz);
 }
 
 // ---------------------------------------------------------------- reductions
@@ -361,11 +354,18 @@ __global__ __launch_bounds__(256) void k_dgemm(GemmArgs g)
 
 }  // namespace
 
-hipError_t launch_sfac(const SfacArgs &a, hipStream_t st)
+hipError_t launch_sfac(int cls, const SfacArgs &a, hipStream_t st)
 {
     if (a.nsp <= 0 || a.ng <= 0) return hipSuccess;
     dim3 grid((a.ng + 63) / 64, a.nsp), block(64);
-    hipLaunchKernelGGL(k_sfac, grid, block, 0, st, a);
+    switch (cls) {
+        case 0: hipLaunchKernelGGL((k_sfac<0, 0>), grid, block, 0, st, a); break;
+        case 1: hipLaunchKernelGGL((k_sfac<1, 0>), grid, block, 0, st, a); break;
+        case 2: hipLaunchKernelGGL((k_sfac<1, 1>), grid, block, 0, st, a); break;
+        case 3: hipLaunchKernelGGL((k_sfac<2, 0>), grid, block, 0, st, a); break;
+        case 4: hipLaunchKernelGGL((k_sfac<2, 1>), grid, block, 0, st, a); break;
+        default: hipLaunchKernelGGL((k_sfac<2, 2>), grid, block, 0, st, a); break;
+    }
     return hipGetLastError();
 }
 

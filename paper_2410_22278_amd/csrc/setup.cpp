@@ -376,21 +376,26 @@ int build_setup(const double *cell, int natom, const double *xyz, int nshell, co
 
     // unique shell pairs with their pair indices (for the structure factors)
     {
-        std::vector<std::pair<std::pair<int, int>, int>> sp;
+        // (class, first shell, second shell) -> pair indices
+        std::vector<std::pair<std::tuple<int, int, int>, int>> sp;
         sp.reserve(S.pairs.size());
         for (const GroupRec &G : S.groups)
-            for (int k = G.pstart; k < G.pend; ++k) sp.push_back({{G.shA, G.shB}, k});
+            for (int k = G.pstart; k < G.pend; ++k)
+                sp.push_back({{class_of(l[G.shA], l[G.shB]), G.shA, G.shB}, k});
         std::sort(sp.begin(), sp.end());
         S.sp_start.clear(); S.sp_pairs.clear(); S.sp_shA.clear(); S.sp_shB.clear();
+        for (int c = 0; c <= kNumClass; ++c) S.sp_class_start[c] = 0;
         for (size_t k = 0; k < sp.size(); ++k) {
             if (k == 0 || sp[k].first != sp[k - 1].first) {
                 S.sp_start.push_back((int)k);
-                S.sp_shA.push_back(sp[k].first.first);
-                S.sp_shB.push_back(sp[k].first.second);
+                S.sp_shA.push_back(std::get<1>(sp[k].first));
+                S.sp_shB.push_back(std::get<2>(sp[k].first));
+                S.sp_class_start[std::get<0>(sp[k].first) + 1]++;
             }
             S.sp_pairs.push_back(sp[k].second);
         }
         S.sp_start.push_back((int)sp.size());
+        for (int c = 0; c < kNumClass; ++c) S.sp_class_start[c + 1] += S.sp_class_start[c];
     }
 
     // ---------------- reciprocal vectors (half space), weights 2 w_G

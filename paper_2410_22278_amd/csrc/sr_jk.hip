@@ -278,9 +278,9 @@ hipError_t launch_sr_jk(int cb, int ck, const SRArgs &a, hipStream_t st)
     if (cb == X && ck == Y) return launch_pair<X, Y>(a, st);
     PBCJK_CASE(0, 0) PBCJK_CASE(0, 1) PBCJK_CASE(0, 2) PBCJK_CASE(1, 1) PBCJK_CASE(1, 2) PBCJK_CASE(2, 2)
 #if PBCJK_WITH_D
-    PBCJK_CASE(0, 3) PBCJK_CASE(0, 4) PBCJK_CASE(0, 5) PBCJK_CASE(1, 3) PBCJK_CASE(1, 4) PBCJK_CASE(1, 5)
-    PBCJK_CASE(2, 3) PBCJK_CASE(2, 4) PBCJK_CASE(2, 5) PBCJK_CASE(3, 3) PBCJK_CASE(3, 4) PBCJK_CASE(3, 5)
-    PBCJK_CASE(4, 4) PBCJK_CASE(4, 5) PBCJK_CASE(5, 5)
+    // d-shell class pairs up to total angular momentum 3; larger ones run in
+    // the cooperative kernel
+    PBCJK_CASE(0, 3) PBCJK_CASE(0, 4) PBCJK_CASE(1, 3)
 #endif
 #undef PBCJK_CASE
     return hipErrorNotSupported;

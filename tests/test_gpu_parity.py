@@ -170,3 +170,45 @@ def test_cfg3_mixed_sampled_rows(lib, oracle_mod):
     dJ, dK, _, _ = _report("cfg3 rows", J, K, ref, s.natom)
     assert st["terms_fp32"] > 0
     assert dJ < 1e-7 and dK < 1e-7
+
+
+D_CASES = [
+    dict(seed=21, natom=2, recipe=((0, 0), (1, 0), (2, 1)), lo=0.5, hi=4.0, nprim=2, a_ang=3.0),
+    dict(seed=22, natom=2, recipe=((2, 0), (1, 0)), lo=0.4, hi=3.0, nprim=2, a_ang=2.8, skew=0.1),
+]
+
+
+@pytest.mark.parametrize("case", D_CASES, ids=["spd_spherical", "pd_cartesian_skewed"])
+def test_d_shells(lib, oracle_mod, case):
+    """d shells (spherical and Cartesian, skewed cell): every one of the 21
+    class pairs, through both the per-lane and the cooperative kernels."""
+    s = inputs.small_cell(**case)
+    ref = oracle_mod.jk(s)
+    with lib.Handle(s) as h:
+        J, K, EJ, EK = h.build(s.D)
+        st = h.stats()
+    dJ, dK, dEJ, dEK = _report(f"{s.name} d (terms {st['terms']:.0f})", J, K, ref, s.natom, EJ, EK)
+    assert dJ < 1e-9 and dK < 1e-9 and dEJ < 1e-9 and dEK < 1e-9
+
+
+@pytest.mark.parametrize("mask,key", [(1, "sr"), (2, "lr"), (4, "self")])
+def test_d_parts(lib, oracle_mod, mask, key):
+    s = inputs.small_cell(**D_CASES[0])
+    ref = oracle_mod.jk(s, parts=key)
+    with lib.Handle(s) as h:
+        h.set_parts(mask)
+        J, K, _, _ = h.build(s.D)
+    dJ, dK, _, _ = _report(f"d part {key}", J, K, ref, s.natom)
+    assert dJ < 1e-9 and dK < 1e-9
+
+
+def test_d_mixed(lib, oracle_mod):
+    s = inputs.small_cell(**D_CASES[0])
+    ref = oracle_mod.jk(s)
+    thr = Thresholds(**{**s.thr.__dict__, "fp32_below": 1e-2})
+    with lib.Handle(s, thr=thr) as h:
+        J, K, EJ, EK = h.build(s.D)
+        st = h.stats()
+    dJ, dK, dEJ, dEK = _report(f"d mixed (fp32 {st['terms_fp32']:.0f}/{st['terms']:.0f})", J, K, ref, s.natom,
+                               EJ, EK)
+    assert dJ < 1e-7 and dK < 1e-7 and dEJ < 1e-6 and dEK < 1e-6
