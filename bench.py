@@ -172,7 +172,9 @@ def main():
     sr_ms = stage["sr"]
     sr_ach = sr_fl / (sr_ms * 1e-3) / 1e12 if sr_ms > 0 else 0.0
     roof_gemm = {
-        "kernel": "k_dgemm (reciprocal-space K: T_G = F_G D, K += W_G T_G F_G)",
+        "kernel": ("k_dgemm (reciprocal-space K: Y_G = F_G L, K += W_G Y_G Y_G^T, D = L L^T)"
+                   if st["lr_rank"] >= 0 else
+                   "k_dgemm (reciprocal-space K: T_G = F_G D, K += W_G T_G F_G)"),
         "bound": "mfma", "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
         "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": None,
         "launches_per_build": n_gemm / args.steps, "avg_launch_ms": gemm_ms / max(1, n_gemm),
@@ -216,6 +218,8 @@ def main():
         "terms_per_build": terms,
         "terms_fp32_per_build": st["terms_fp32"],
         "group_pairs": st["n_group_pairs"],
+        "lr_exchange": {"form": "low-rank" if st["lr_rank"] >= 0 else "dense",
+                        "density_rank": st["lr_rank"], "factor_ms": st["t_chol_ms"]},
         "stage_ms_per_build": {k: v / args.steps for k, v in stage.items()},
         "E_J": EJ,
         "E_K": EK,

@@ -40,6 +40,8 @@
 #ifndef PBCJK_H
 #define PBCJK_H
 
+#include <stddef.h>
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -49,6 +51,8 @@ extern "C" {
 #define PBC_JK_ENOMEM (-2)   /* device or host allocation failed, or over the HBM budget */
 #define PBC_JK_EDEVICE (-3)  /* HIP runtime error; the handle is unusable                 */
 #define PBC_JK_ENOTSUP (-4)  /* request outside what the library implements             */
+#define PBC_JK_ECANCELED (-5) /* server request cancelled before its build started       */
+#define PBC_JK_EBUSY (-6)    /* server request already running: too late to cancel       */
 
 typedef struct pbc_jk pbc_jk; /* opaque handle */
 
@@ -126,6 +130,9 @@ typedef struct {
                                with classes ss, ps, pp, ds, dp, dd                      */
     double n_group_pairs; /* entries of the real-space neighbour lists (group pairs that can
                                have a term for some density)                            */
+    double lr_rank;      /* last build: rank of the density factor used by the reciprocal
+                            exchange, or -1 when the dense form was used                */
+    double t_chol_ms;    /* last build: duration of the density factorisation and its check */
 } pbc_jk_counters;
 
 /* Creates a handle: validates and copies the inputs, builds the local pair
@@ -164,6 +171,100 @@ int pbc_jk_stats(const pbc_jk *h, pbc_jk_counters *out);
 #define PBC_JK_PART_LR 2
 #define PBC_JK_PART_SELF 4
 int pbc_jk_set_parts(pbc_jk *h, int mask);
+
+/* Form of the reciprocal exchange K_LR = sum_G W_G (A_G D A_G + B_G D B_G)
+ * (Sec. 2.4; A, B the real and imaginary pair structure factors):
+ *   PBC_JK_LR_AUTO  (default) factor D = L L^T by pivoted Cholesky on the
+ *                   device, stopping when every remaining diagonal entry is
+ *                   <= tol * max diag(D), and use K_LR = sum_G W_G (Y Y^T)
+ *                   with Y = A_G L and B_G L; the factor is accepted only if
+ *                   max |D - L L^T| <= 2 tol max diag(D) + 4 n eps max diag(D)
+ *                   and its rank is at most 3/4 of the Cartesian AO count,
+ *                   otherwise the dense form runs.  The choice is made on the
+ *                   device per build (no host synchronisation).
+ *   PBC_JK_LR_DENSE always the dense form T_G = A_G D, K_LR += W_G T_G A_G.
+ * tol <= 0 keeps the current tolerance (default 1e-13).  EINVAL for an
+ * unknown mode or a NULL handle. */
+#define PBC_JK_LR_AUTO 0
+#define PBC_JK_LR_DENSE 1
+int pbc_jk_set_lr(pbc_jk *h, int mode, double tol);
+
+/* ------------------------------------------------------------------------
+ * Request server: Fock builds for many cells, as an SCF or MD driver issues
+ * them.  Requests are queued in arrival order and run on `slots` worker
+ * threads, each build on its own HIP stream, so builds of different cells
+ * overlap on the device.  All device memory of the server comes from one
+ * arena of `hbm_budget` bytes allocated at creation (no hipMalloc/hipFree per
+ * request).  A request for a new cell is admitted when its footprint (setup
+ * data, work buffers and neighbour lists) fits in the free part of the arena;
+ * the first new-cell request that does not fit blocks later new-cell
+ * requests (no starvation), while requests for cells already resident run
+ * as soon as their cell is idle.  With cache_cells set, a cell's setup data
+ * stays resident after its build and later requests with identical cell,
+ * atoms, basis, omega and thresholds reuse it; idle cells are evicted
+ * least-recently-used when memory is needed.  A request whose footprint
+ * exceeds the whole budget fails with PBC_JK_ENOMEM; a bad input fails only
+ * its own request.
+ * ------------------------------------------------------------------------ */
+typedef struct pbc_jk_server pbc_jk_server;
+
+typedef struct {
+    size_t hbm_budget;    /* arena bytes; 0 = half of the device's free memory           */
+    int slots;            /* concurrent builds (worker threads / streams); 0 = 4            */
+    int cache_cells;      /* keep idle cells resident for reuse (0/1)                       */
+    double lr_budget_mb;  /* per-cell reciprocal-sum chunk budget; 0 = 1024 MB              */
+} pbc_jk_server_config;
+
+typedef struct {
+    int status;           /* 0 or the request's error code                                  */
+    int cache_hit;        /* 1 when the cell's setup data was already resident              */
+    int retries;          /* admissions retried after the budget was short                  */
+    int nbf;              /* output AOs                                                     */
+    double queue_ms;      /* submit -> start of work on a worker                            */
+    double setup_ms;      /* host setup + device creation (0 on a cache hit)                */
+    double build_ms;      /* the build itself, D in to J, K, E out                          */
+    double latency_ms;    /* submit -> completion                                           */
+    size_t device_bytes;  /* device bytes the cell holds                                    */
+    char error[160];      /* message when status != 0                                       */
+} pbc_jk_request_info;
+
+typedef struct {
+    long submitted, completed, failed, cancelled, cache_hits, evictions, retries;
+    int slots;
+    int peak_running;     /* most requests in work (setup or build) at once                 */
+    size_t budget;        /* arena bytes                                                    */
+    size_t in_use;        /* arena bytes held now                                           */
+    size_t peak_in_use;   /* most arena bytes held at once                                  */
+} pbc_jk_server_counters;
+
+/* cfg may be NULL (defaults).  ENOMEM when the arena cannot be allocated. */
+int pbc_jk_server_create(const pbc_jk_server_config *cfg, pbc_jk_server **out);
+
+/* Queues one build.  The cell, atoms, basis, thresholds and D (nbf x nbf,
+ * host) are copied before the call returns; J and K (host, nbf x nbf, either
+ * may be NULL) and E_J/E_K (may be NULL) must stay valid until
+ * pbc_jk_server_wait returns for the ticket.  EINVAL for missing inputs. */
+int pbc_jk_server_submit(pbc_jk_server *s, const pbc_cell *cell, const pbc_atoms *atoms,
+                         const pbc_basis *basis, double omega, const pbc_jk_thresholds *thr,
+                         const double *D, double *J, double *K, double *E_J, double *E_K,
+                         unsigned long long *ticket);
+
+/* Blocks until the request is done; fills *info (may be NULL) and returns the
+ * request's status.  Each ticket is waited for once; EINVAL for an unknown
+ * ticket. */
+int pbc_jk_server_wait(pbc_jk_server *s, unsigned long long ticket, pbc_jk_request_info *info);
+
+/* Cancels a request that has not started its build: it completes with
+ * PBC_JK_ECANCELED.  A build already running finishes normally.  Returns 0
+ * when the request will be cancelled, PBC_JK_EBUSY when it is too late,
+ * EINVAL for an unknown ticket. */
+int pbc_jk_server_cancel(pbc_jk_server *s, unsigned long long ticket);
+
+int pbc_jk_server_stats(pbc_jk_server *s, pbc_jk_server_counters *out);
+
+/* Cancels queued requests, waits for running builds, releases everything.
+ * Tickets not yet waited for become invalid.  NULL is accepted. */
+void pbc_jk_server_destroy(pbc_jk_server *s);
 
 /* Message of the last error on this thread ("" if none). */
 const char *pbc_jk_last_error(void);

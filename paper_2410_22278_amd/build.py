@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpbcjk.so")
 OBJDIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["setup.cpp", "sr_jk.hip", "sr_coop.hip", "nbr.hip", "lr.hip", "api.hip"]
+SOURCES = ["setup.cpp", "sr_jk.hip", "sr_coop.hip", "nbr.hip", "lr.hip", "api.hip", "server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

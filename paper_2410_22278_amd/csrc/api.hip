@@ -9,6 +9,8 @@
 #include <string>
 #include <vector>
 
+#include "arena.h"
+#include "handle.h"
 #include "kernels.h"
 #include "pbcjk.h"
 
@@ -32,31 +34,20 @@ int fail(int code, const std::string &msg)
         if (e_ != hipSuccess) return fail(PBC_JK_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-template <class T>
-int dalloc(T **p, size_t n)
-{
-    *p = nullptr;
-    if (n == 0) n = 1;
-    hipError_t e = hipMalloc((void **)p, n * sizeof(T));
-    if (e != hipSuccess) return fail(PBC_JK_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
-    return 0;
-}
-
-template <class T>
-int upload(T **p, const std::vector<T> &v)
-{
-    int rc = dalloc(p, v.size());
-    if (rc) return rc;
-    if (!v.empty()) HIPCHK(hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
-    return 0;
-}
-
 }  // namespace
 
 struct pbc_jk {
     Setup S;
     int device = 0;
+    Arena *arena = nullptr;      // device memory source; NULL = hipMalloc
+    size_t dev_bytes = 0;        // device bytes held
+    bool profile = true;         // per-launch timing events (GEMM, structure factors)
+    double lr_budget_mb = 0.0;   // reciprocal chunk budget; 0 = default
+    bool dry = false;            // count device bytes only (no allocation, no copies)
+    size_t dry_bytes = 0;
     int parts = PBC_JK_PART_SR | PBC_JK_PART_LR | PBC_JK_PART_SELF;
+    int lr_mode = PBC_JK_LR_AUTO;
+    double lr_tol = 1e-13;
     hipStream_t own = nullptr;
     // setup data
     PairRec *d_pairs = nullptr;
@@ -72,13 +63,21 @@ struct pbc_jk {
     unsigned long long *d_dmaxg = nullptr, *d_cnt = nullptr;
     // real-space neighbour lists, one segment per class pair
     int *d_nbr_bra = nullptr, *d_nbr_ket = nullptr;
+    // low-rank reciprocal exchange: density factor (by columns), work, control
+    double *d_L = nullptr, *d_pw = nullptr;
+    int *d_pwi = nullptr, *d_ctl = nullptr;
+    int lr_rmax = 0;
+    bool lr_ran = false;
+    size_t nbr_bytes_needed = 0;   // set once the neighbour lists are counted
     long nbr_off[22] = {0};
     int gchunk = 0;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     // event pairs around GEMM and structure-factor launches of one build
     static constexpr int kMaxTimed = 256;
     std::vector<hipEvent_t> tev;
-    std::vector<int> tkind;      // 0 = GEMM, 1 = structure factors
+    // 0 = GEMM, 1 = structure factors, 2 = low-rank GEMM (flops per unit rank),
+    // 3 = dense GEMM run only when the factor is rejected, 4 = factorisation
+    std::vector<int> tkind;
     std::vector<double> tflops;
     int ntimed = 0;
     bool timed = false;
@@ -87,20 +86,83 @@ struct pbc_jk {
 
 namespace {
 
+template <class T>
+int dalloc(pbc_jk *h, T **p, size_t n)
+{
+    *p = nullptr;
+    if (n == 0) n = 1;
+    const size_t bytes = n * sizeof(T);
+    if (h->dry) {
+        h->dry_bytes += Arena::round_up(bytes);
+        return 0;
+    }
+    if (h->arena) {
+        *p = (T *)h->arena->alloc(bytes);
+        if (!*p) return fail(PBC_JK_ENOMEM, "device memory budget exhausted");
+        h->dev_bytes += Arena::round_up(bytes);
+        return 0;
+    }
+    hipError_t e = hipMalloc((void **)p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(PBC_JK_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    h->dev_bytes += bytes;
+    return 0;
+}
+
+void dfree(pbc_jk *h, void *p)
+{
+    if (!p) return;
+    if (h->arena && h->arena->owns(p)) {
+        h->arena->release(p);
+        return;
+    }
+    (void)hipFree(p);
+}
+
+template <class T>
+int upload(pbc_jk *h, T **p, const std::vector<T> &v)
+{
+    int rc = dalloc(h, p, v.size());
+    if (rc || h->dry) return rc;
+    if (!v.empty()) HIPCHK(hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return 0;
+}
+
+// Frees the device buffers (pointers reset; streams, events and the host
+// setup are kept, so the device part can be created again).
+void release_device(pbc_jk *h)
+{
+    void **pp[] = {(void **)&h->d_pairs, (void **)&h->d_groups, (void **)&h->d_boys, (void **)&h->d_S,
+                   (void **)&h->d_G, (void **)&h->d_Gw, (void **)&h->d_sp_start, (void **)&h->d_sp_pairs,
+                   (void **)&h->d_sp_shA, (void **)&h->d_sp_shB, (void **)&h->d_sh_l, (void **)&h->d_sh_aoc,
+                   (void **)&h->d_tr_ao, (void **)&h->d_inv_ci, (void **)&h->d_tr_c, (void **)&h->d_dscale,
+                   (void **)&h->d_inv_cc, (void **)&h->d_D, (void **)&h->d_Dt, (void **)&h->d_Dmax,
+                   (void **)&h->d_X, (void **)&h->d_Y, (void **)&h->d_Jt, (void **)&h->d_Kt, (void **)&h->d_F,
+                   (void **)&h->d_T, (void **)&h->d_rho, (void **)&h->d_scal, (void **)&h->d_Jo,
+                   (void **)&h->d_Ko, (void **)&h->d_dmaxg, (void **)&h->d_cnt, (void **)&h->d_nbr_bra,
+                   (void **)&h->d_nbr_ket, (void **)&h->d_L, (void **)&h->d_pw, (void **)&h->d_pwi,
+                   (void **)&h->d_ctl};
+    for (void **p : pp) {
+        dfree(h, *p);
+        *p = nullptr;
+    }
+    h->dev_bytes = 0;
+    h->timed = false;
+}
+
 void release(pbc_jk *h)
 {
-    void *ptrs[] = {h->d_pairs, h->d_groups, h->d_boys, h->d_S, h->d_G, h->d_Gw, h->d_sp_start, h->d_sp_pairs,
-                    h->d_sp_shA, h->d_sp_shB, h->d_sh_l, h->d_sh_aoc, h->d_tr_ao, h->d_inv_ci, h->d_tr_c,
-                    h->d_dscale, h->d_inv_cc, h->d_D, h->d_Dt, h->d_Dmax, h->d_X, h->d_Y, h->d_Jt, h->d_Kt,
-                    h->d_F, h->d_T, h->d_rho, h->d_scal, h->d_Jo, h->d_Ko, h->d_dmaxg, h->d_cnt,
-                    h->d_nbr_bra, h->d_nbr_ket};
-    for (void *p : ptrs)
-        if (p) (void)hipFree(p);
+    release_device(h);
     for (auto &e : h->ev)
         if (e) (void)hipEventDestroy(e);
     for (auto &e : h->tev)
         if (e) (void)hipEventDestroy(e);
     if (h->own) (void)hipStreamDestroy(h->own);
+    h->own = nullptr;
+    for (auto &e : h->ev) e = nullptr;
+    h->tev.clear();
 }
 
 // Brackets one launch with a pair of events (up to kMaxTimed per build).
@@ -110,7 +172,7 @@ struct TimedLaunch {
     int slot = -1;
     TimedLaunch(pbc_jk *h_, hipStream_t st_, int kind, double flops) : h(h_), st(st_)
     {
-        if (h->ntimed < pbc_jk::kMaxTimed) {
+        if (h->profile && h->ntimed < pbc_jk::kMaxTimed) {
             slot = h->ntimed++;
             h->tkind[slot] = kind;
             h->tflops[slot] = flops;
@@ -128,29 +190,34 @@ int build_neighbours(pbc_jk *h);
 int create_device(pbc_jk *h)
 {
     Setup &S = h->S;
-    HIPCHK(hipGetDevice(&h->device));
-    HIPCHK(hipStreamCreateWithFlags(&h->own, hipStreamNonBlocking));
-    for (auto &e : h->ev) HIPCHK(hipEventCreate(&e));
-    h->tev.assign(2 * pbc_jk::kMaxTimed, nullptr);
-    h->tkind.assign(pbc_jk::kMaxTimed, 0);
-    h->tflops.assign(pbc_jk::kMaxTimed, 0.0);
-    for (auto &e : h->tev) HIPCHK(hipEventCreate(&e));
+    if (!h->dry) {
+        HIPCHK(hipGetDevice(&h->device));
+        if (!h->own) HIPCHK(hipStreamCreateWithFlags(&h->own, hipStreamNonBlocking));
+        for (auto &e : h->ev)
+            if (!e) HIPCHK(hipEventCreate(&e));
+        if (h->profile && h->tev.empty()) {
+            h->tev.assign(2 * pbc_jk::kMaxTimed, nullptr);
+            h->tkind.assign(pbc_jk::kMaxTimed, 0);
+            h->tflops.assign(pbc_jk::kMaxTimed, 0.0);
+            for (auto &e : h->tev) HIPCHK(hipEventCreate(&e));
+        }
+    }
     int rc;
-    if ((rc = upload(&h->d_pairs, S.pairs))) return rc;
-    if ((rc = upload(&h->d_groups, S.groups))) return rc;
-    if ((rc = upload(&h->d_boys, S.boys))) return rc;
-    if ((rc = upload(&h->d_S, S.S))) return rc;
-    if ((rc = upload(&h->d_G, S.G))) return rc;
-    if ((rc = upload(&h->d_Gw, S.Gw))) return rc;
-    if ((rc = upload(&h->d_sp_start, S.sp_start))) return rc;
-    if ((rc = upload(&h->d_sp_pairs, S.sp_pairs))) return rc;
-    if ((rc = upload(&h->d_sp_shA, S.sp_shA))) return rc;
-    if ((rc = upload(&h->d_sp_shB, S.sp_shB))) return rc;
-    if ((rc = upload(&h->d_sh_l, S.sh_l))) return rc;
-    if ((rc = upload(&h->d_sh_aoc, S.sh_aoc))) return rc;
-    if ((rc = upload(&h->d_tr_ao, S.tr_ao))) return rc;
-    if ((rc = upload(&h->d_tr_c, S.tr_c))) return rc;
-    if ((rc = upload(&h->d_dscale, S.dscale))) return rc;
+    if ((rc = upload(h, &h->d_pairs, S.pairs))) return rc;
+    if ((rc = upload(h, &h->d_groups, S.groups))) return rc;
+    if ((rc = upload(h, &h->d_boys, S.boys))) return rc;
+    if ((rc = upload(h, &h->d_S, S.S))) return rc;
+    if ((rc = upload(h, &h->d_G, S.G))) return rc;
+    if ((rc = upload(h, &h->d_Gw, S.Gw))) return rc;
+    if ((rc = upload(h, &h->d_sp_start, S.sp_start))) return rc;
+    if ((rc = upload(h, &h->d_sp_pairs, S.sp_pairs))) return rc;
+    if ((rc = upload(h, &h->d_sp_shA, S.sp_shA))) return rc;
+    if ((rc = upload(h, &h->d_sp_shB, S.sp_shB))) return rc;
+    if ((rc = upload(h, &h->d_sh_l, S.sh_l))) return rc;
+    if ((rc = upload(h, &h->d_sh_aoc, S.sh_aoc))) return rc;
+    if ((rc = upload(h, &h->d_tr_ao, S.tr_ao))) return rc;
+    if ((rc = upload(h, &h->d_tr_c, S.tr_c))) return rc;
+    if ((rc = upload(h, &h->d_dscale, S.dscale))) return rc;
     // inverse transform: output AO -> up to three (Cartesian index, coefficient)
     std::vector<int> ici(3 * S.nbf, -1);
     std::vector<double> icc(3 * S.nbf, 0.0);
@@ -164,31 +231,38 @@ int create_device(pbc_jk *h)
             ici[3 * a + k] = i;
             icc[3 * a + k] = S.tr_c[2 * i + u];
         }
-    if ((rc = upload(&h->d_inv_ci, ici))) return rc;
-    if ((rc = upload(&h->d_inv_cc, icc))) return rc;
+    if ((rc = upload(h, &h->d_inv_ci, ici))) return rc;
+    if ((rc = upload(h, &h->d_inv_cc, icc))) return rc;
 
     const size_t n2 = (size_t)S.nbfc * S.nbfc, m2 = (size_t)S.nbf * S.nbf;
-    if ((rc = dalloc(&h->d_D, m2))) return rc;
-    if ((rc = dalloc(&h->d_Dt, n2))) return rc;
-    if ((rc = dalloc(&h->d_Dmax, (size_t)S.nshell * S.nshell))) return rc;
-    if ((rc = dalloc(&h->d_X, n2))) return rc;
-    if ((rc = dalloc(&h->d_Y, n2))) return rc;
-    if ((rc = dalloc(&h->d_Jt, n2))) return rc;
-    if ((rc = dalloc(&h->d_Kt, n2))) return rc;
-    if ((rc = dalloc(&h->d_Jo, m2))) return rc;
-    if ((rc = dalloc(&h->d_Ko, m2))) return rc;
-    if ((rc = dalloc(&h->d_scal, 4))) return rc;
-    if ((rc = dalloc(&h->d_dmaxg, 1))) return rc;
-    if ((rc = dalloc(&h->d_cnt, 32))) return rc;
+    if ((rc = dalloc(h, &h->d_D, m2))) return rc;
+    if ((rc = dalloc(h, &h->d_Dt, n2))) return rc;
+    if ((rc = dalloc(h, &h->d_Dmax, (size_t)S.nshell * S.nshell))) return rc;
+    if ((rc = dalloc(h, &h->d_X, n2))) return rc;
+    if ((rc = dalloc(h, &h->d_Y, n2))) return rc;
+    if ((rc = dalloc(h, &h->d_Jt, n2))) return rc;
+    if ((rc = dalloc(h, &h->d_Kt, n2))) return rc;
+    if ((rc = dalloc(h, &h->d_Jo, m2))) return rc;
+    if ((rc = dalloc(h, &h->d_Ko, m2))) return rc;
+    if ((rc = dalloc(h, &h->d_scal, 4))) return rc;
+    if ((rc = dalloc(h, &h->d_dmaxg, 1))) return rc;
+    if ((rc = dalloc(h, &h->d_cnt, 32))) return rc;
     // reciprocal-space chunk: F and T hold 2 * gchunk matrices each
     const int nG = (int)S.Gw.size();
-    double budget_mb = 16384.0;
+    double budget_mb = h->lr_budget_mb > 0 ? h->lr_budget_mb : 16384.0;
     if (const char *e = std::getenv("PBCJK_LR_BUDGET_MB")) budget_mb = std::max(64.0, std::atof(e));
     long per = (long)(budget_mb * 1048576.0 / (4.0 * 8.0 * (double)n2));
     h->gchunk = (int)std::max(1L, std::min<long>(per, std::max(nG, 1)));
-    if ((rc = dalloc(&h->d_F, 2 * (size_t)h->gchunk * n2))) return rc;
-    if ((rc = dalloc(&h->d_T, std::max<size_t>(2 * (size_t)h->gchunk * n2, n2)))) return rc;
-    if ((rc = dalloc(&h->d_rho, 2 * (size_t)h->gchunk))) return rc;
+    if ((rc = dalloc(h, &h->d_F, 2 * (size_t)h->gchunk * n2))) return rc;
+    if ((rc = dalloc(h, &h->d_T, std::max<size_t>(2 * (size_t)h->gchunk * n2, n2)))) return rc;
+    if ((rc = dalloc(h, &h->d_rho, 2 * (size_t)h->gchunk))) return rc;
+    const int n = S.nbfc, nblk = (n + 63) / 64;
+    h->lr_rmax = std::max(1, (3 * n) / 4);
+    if ((rc = dalloc(h, &h->d_L, (size_t)n * h->lr_rmax))) return rc;
+    if ((rc = dalloc(h, &h->d_pw, (size_t)n + 2 * nblk + 4))) return rc;
+    if ((rc = dalloc(h, &h->d_pwi, 2 * (size_t)nblk))) return rc;
+    if ((rc = dalloc(h, &h->d_ctl, 4))) return rc;
+    if (h->dry) return 0;
     return build_neighbours(h);
 }
 
@@ -216,8 +290,15 @@ int build_neighbours(pbc_jk *h)
     int *d_counts = nullptr;
     long *d_offs = nullptr;
     int rc;
-    if ((rc = dalloc(&d_counts, std::max(1, maxnb)))) return rc;
-    if ((rc = dalloc(&d_offs, std::max(1, maxnb)))) { (void)hipFree(d_counts); return rc; }
+    struct Tmp {
+        pbc_jk *h;
+        void *a = nullptr, *b = nullptr;
+        ~Tmp() { dfree(h, a); dfree(h, b); }
+    } tmp{h};
+    if ((rc = dalloc(h, &d_counts, std::max(1, maxnb)))) return rc;
+    tmp.a = d_counts;
+    if ((rc = dalloc(h, &d_offs, std::max(1, maxnb)))) return rc;
+    tmp.b = d_offs;
     std::vector<std::vector<long>> offs(21);
     std::vector<int> cnt(std::max(1, maxnb));
     long total = 0;
@@ -237,11 +318,10 @@ int build_neighbours(pbc_jk *h)
             for (int i = 0; i < a.nb; ++i) { offs[slot][i] = total; total += cnt[i]; }
         }
     h->nbr_off[21] = total;
-    if ((rc = dalloc(&h->d_nbr_bra, (size_t)std::max(1L, total))) ||
-        (rc = dalloc(&h->d_nbr_ket, (size_t)std::max(1L, total)))) {
-        (void)hipFree(d_counts); (void)hipFree(d_offs);
+    h->nbr_bytes_needed = 2 * Arena::round_up(sizeof(int) * (size_t)std::max(1L, total));
+    if ((rc = dalloc(h, &h->d_nbr_bra, (size_t)std::max(1L, total))) ||
+        (rc = dalloc(h, &h->d_nbr_ket, (size_t)std::max(1L, total))))
         return rc;
-    }
     slot = 0;
     for (int cb = 0; cb < kNumClass; ++cb)
         for (int ck = cb; ck < kNumClass; ++ck, ++slot) {
@@ -254,8 +334,6 @@ int build_neighbours(pbc_jk *h)
             HIPCHK(launch_nbr(a, st));
             HIPCHK(hipStreamSynchronize(st));
         }
-    (void)hipFree(d_counts);
-    (void)hipFree(d_offs);
     h->st.n_group_pairs = (double)total;
     return 0;
 }
@@ -319,6 +397,24 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
         sa.pairs = h->d_pairs; sa.sp_start = h->d_sp_start; sa.sp_pairs = h->d_sp_pairs;
         sa.sp_shA = h->d_sp_shA; sa.sp_shB = h->d_sp_shB; sa.sh_l = h->d_sh_l; sa.sh_aoc = h->d_sh_aoc;
         sa.F = h->d_F; sa.nbfc = n;
+        const int ntile = (n + kGemmTile - 1) / kGemmTile, upper_tiles = ntile * (ntile + 1) / 2;
+        const int rmax = h->lr_rmax;
+        const bool lowrank = wantK && h->lr_mode == PBC_JK_LR_AUTO;
+        h->lr_ran = lowrank;
+        if (lowrank) {
+            // D~ = L L^T on the device; R = L L^T into T, then the entrywise check
+            TimedLaunch tl(h, st, 4, 0.0);
+            HIPCHK(launch_pchol(h->d_Dt, n, h->lr_tol, rmax, h->d_L, h->d_pw, h->d_pwi, h->d_ctl, st));
+            GemmArgs gr{};
+            gr.M = gr.N = n; gr.K = rmax;
+            gr.A = h->d_L; gr.lda = n; gr.sA = 0; gr.transA = 1;
+            gr.B = h->d_L; gr.ldb = n; gr.sB = 0;
+            gr.C = h->d_T; gr.ldc = n; gr.sC = 0;
+            gr.nbatch = 1; gr.alpha0 = 1.0; gr.slices = 1;
+            gr.ctl = h->d_ctl; gr.ctl_mode = 2;
+            HIPCHK(launch_dgemm(gr, st));
+            HIPCHK(launch_lowrank_check(h->d_Dt, h->d_T, n, h->d_pw, h->d_ctl, st));
+        }
         for (int g0 = 0; g0 < nG; g0 += h->gchunk) {
             const int gc = std::min(h->gchunk, nG - g0);
             HIPCHK(launch_fill(h->d_F, 2L * gc * n2, 0.0, st));
@@ -336,27 +432,55 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
                 HIPCHK(launch_jlr(h->d_F, h->d_rho, h->d_Gw + g0, gc, (int)n2, h->d_Jt, st));
             }
             if (wantK) {
+                const double nd = (double)n;
+                if (lowrank) {
+                    // Y_b = F_b L (n x rank), then K += W_b Y_b Y_b^T on the upper tiles
+                    GemmArgs g1{};
+                    g1.M = n; g1.N = rmax; g1.K = n;
+                    g1.A = h->d_F; g1.lda = n; g1.sA = n2;
+                    g1.B = h->d_L; g1.ldb = n; g1.sB = 0; g1.transB = 1;
+                    g1.C = h->d_T; g1.ldc = rmax; g1.sC = (long)n * rmax;
+                    g1.nbatch = 2 * gc; g1.alpha0 = 1.0; g1.slices = 1;
+                    g1.ctl = h->d_ctl; g1.ctl_mode = 1;
+                    {
+                        TimedLaunch tl(h, st, 2, 2.0 * nd * nd * g1.nbatch);
+                        HIPCHK(launch_dgemm(g1, st));
+                    }
+                    for (int half = 0; half < 2; ++half) {
+                        GemmArgs g2{};
+                        g2.M = g2.N = n; g2.K = rmax;
+                        g2.A = h->d_T + (long)half * gc * n * rmax; g2.lda = rmax; g2.sA = (long)n * rmax;
+                        g2.B = g2.A; g2.ldb = rmax; g2.sB = (long)n * rmax; g2.transB = 1;
+                        g2.C = h->d_Kt; g2.ldc = n; g2.sC = 0;
+                        g2.nbatch = gc; g2.alpha = h->d_Gw + g0; g2.alpha0 = 1.0; g2.reduce = 1; g2.upper = 1;
+                        g2.slices = std::max(1, std::min(gc, 2048 / std::max(1, upper_tiles)));
+                        g2.ctl = h->d_ctl; g2.ctl_mode = 2;
+                        TimedLaunch tl(h, st, 2, nd * (nd + 1.0) * g2.nbatch);
+                        HIPCHK(launch_dgemm(g2, st));
+                    }
+                }
+                // dense form: T_b = F_b D, K += W_b T_b F_b on the upper tiles (F_b symmetric)
                 GemmArgs g1{};
                 g1.M = g1.N = g1.K = n;
                 g1.A = h->d_F; g1.lda = n; g1.sA = n2;
                 g1.B = h->d_Dt; g1.ldb = n; g1.sB = 0;
                 g1.C = h->d_T; g1.ldc = n; g1.sC = n2;
                 g1.nbatch = 2 * gc; g1.alpha = nullptr; g1.alpha0 = 1.0; g1.reduce = 0; g1.slices = 1;
+                if (lowrank) { g1.ctl = h->d_ctl; g1.ctl_mode = 3; }
                 {
-                    TimedLaunch tl(h, st, 0, 2.0 * n * (double)n * n * g1.nbatch);
+                    TimedLaunch tl(h, st, lowrank ? 3 : 0, 2.0 * nd * nd * nd * g1.nbatch);
                     HIPCHK(launch_dgemm(g1, st));
                 }
-                // K_LR += sum_b W_b T_b F_b; weights repeat for the real and imaginary halves
                 for (int half = 0; half < 2; ++half) {
                     GemmArgs g2{};
                     g2.M = g2.N = g2.K = n;
                     g2.A = h->d_T + (long)half * gc * n2; g2.lda = n; g2.sA = n2;
                     g2.B = h->d_F + (long)half * gc * n2; g2.ldb = n; g2.sB = n2;
                     g2.C = h->d_Kt; g2.ldc = n; g2.sC = 0;
-                    g2.nbatch = gc; g2.alpha = h->d_Gw + g0; g2.alpha0 = 1.0; g2.reduce = 1;
-                    int tiles = ((n + 127) / 128) * ((n + 127) / 128);
-                    g2.slices = std::max(1, std::min(gc, 2048 / std::max(1, tiles)));
-                    TimedLaunch tl(h, st, 0, 2.0 * n * (double)n * n * g2.nbatch);
+                    g2.nbatch = gc; g2.alpha = h->d_Gw + g0; g2.alpha0 = 1.0; g2.reduce = 1; g2.upper = 1;
+                    g2.slices = std::max(1, std::min(gc, 2048 / std::max(1, upper_tiles)));
+                    if (lowrank) { g2.ctl = h->d_ctl; g2.ctl_mode = 3; }
+                    TimedLaunch tl(h, st, lowrank ? 3 : 0, nd * (nd + 1.0) * nd * g2.nbatch);
                     HIPCHK(launch_dgemm(g2, st));
                 }
             }
@@ -381,18 +505,18 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
             g1.nbatch = 1; g1.alpha0 = 1.0; g1.reduce = 0; g1.slices = 1;
             HIPCHK(launch_dgemm(g1, st));
             GemmArgs g2 = g1;
-            g2.A = h->d_T; g2.B = h->d_S; g2.C = h->d_Kt; g2.alpha0 = f; g2.reduce = 1;
+            g2.A = h->d_T; g2.B = h->d_S; g2.C = h->d_Kt; g2.alpha0 = f; g2.reduce = 1; g2.upper = 1;
             HIPCHK(launch_dgemm(g2, st));
         }
     }
 
     // B8: symmetrise, back-transform, energies
     if (wantJ) {
-        FinalArgs fa{h->d_X, h->d_Jt, n, nb, h->d_inv_ci, h->d_inv_cc, Jo};
+        FinalArgs fa{h->d_X, h->d_Jt, n, nb, 0, h->d_inv_ci, h->d_inv_cc, Jo};
         HIPCHK(launch_final(fa, st));
     }
     if (wantK) {
-        FinalArgs fa{h->d_Y, h->d_Kt, n, nb, h->d_inv_ci, h->d_inv_cc, Ko};
+        FinalArgs fa{h->d_Y, h->d_Kt, n, nb, 1, h->d_inv_ci, h->d_inv_cc, Ko};
         HIPCHK(launch_final(fa, st));
     }
     if (E_J || E_K) {
@@ -421,18 +545,13 @@ bool finite_all(const double *p, size_t n)
 
 }  // namespace
 
-extern "C" {
+namespace pbcjk {
 
-const char *pbc_jk_last_error(void) { return g_err.c_str(); }
-
-int pbc_jk_create(const pbc_cell *cell, const pbc_atoms *atoms, const pbc_basis *basis, double omega,
-                  const pbc_jk_thresholds *thr, pbc_jk **out)
+int handle_new(const pbc_cell *cell, const pbc_atoms *atoms, const pbc_basis *basis, double omega,
+               const pbc_jk_thresholds *thr, pbc_jk **out)
 {
-    g_err.clear();
-    if (!out) return fail(PBC_JK_EINVAL, "out is NULL");
     *out = nullptr;
     if (!cell || !atoms || !basis) return fail(PBC_JK_EINVAL, "cell, atoms and basis are required");
-    auto t0 = std::chrono::steady_clock::now();
     double th[8] = {1e-14, 1e-14, 1e-14, 1e-14, 1e-14, 0.0, 0.0, 0.0};
     if (thr) {
         th[0] = thr->pair_R; th[1] = thr->pair_cs; th[2] = thr->ewald_R; th[3] = thr->ewald_K;
@@ -460,17 +579,82 @@ int pbc_jk_create(const pbc_cell *cell, const pbc_atoms *atoms, const pbc_basis 
             return fail(PBC_JK_ENOTSUP, "d shells are not supported by this build");
         }
 #endif
-    rc = create_device(h);
-    if (rc) {
-        std::string keep = g_err;
-        release(h);
-        delete h;
-        g_err = keep;
-        return rc;
-    }
     const Setup &S = h->S;
     h->st.nbf = S.nbf; h->st.nbf_cart = S.nbfc; h->st.n_pairs = (long)S.pairs.size();
     h->st.n_groups = (long)S.groups.size(); h->st.n_gvec = (int)S.Gw.size(); h->st.omega = S.omega;
+    *out = h;
+    return 0;
+}
+
+size_t handle_fixed_bytes(pbc_jk *h, double lr_budget_mb)
+{
+    const double keep = h->lr_budget_mb;
+    h->lr_budget_mb = lr_budget_mb;
+    h->dry = true;
+    h->dry_bytes = 0;
+    (void)create_device(h);
+    h->dry = false;
+    h->lr_budget_mb = keep;
+    return h->dry_bytes;
+}
+
+int handle_device(pbc_jk *h, Arena *arena, bool profile, double lr_budget_mb)
+{
+    h->arena = arena;
+    h->profile = profile;
+    h->lr_budget_mb = lr_budget_mb;
+    int rc = create_device(h);
+    if (rc) {
+        std::string keep = g_err;
+        release_device(h);
+        g_err = keep;
+    }
+    return rc;
+}
+
+void handle_drop_device(pbc_jk *h)
+{
+    (void)hipSetDevice(h->device);
+    if (h->own) (void)hipStreamSynchronize(h->own);
+    release_device(h);
+}
+
+size_t handle_nbr_bytes(const pbc_jk *h) { return h->nbr_bytes_needed; }
+size_t handle_dev_bytes(const pbc_jk *h) { return h->dev_bytes; }
+int handle_natom(const pbc_jk *h) { return (int)h->S.natom; }
+
+void handle_delete(pbc_jk *h)
+{
+    if (!h) return;
+    (void)hipSetDevice(h->device);
+    if (h->own) (void)hipStreamSynchronize(h->own);
+    release(h);
+    delete h;
+}
+
+}  // namespace pbcjk
+
+extern "C" {
+
+const char *pbc_jk_last_error(void) { return g_err.c_str(); }
+
+int pbc_jk_create(const pbc_cell *cell, const pbc_atoms *atoms, const pbc_basis *basis, double omega,
+                  const pbc_jk_thresholds *thr, pbc_jk **out)
+{
+    g_err.clear();
+    if (!out) return fail(PBC_JK_EINVAL, "out is NULL");
+    *out = nullptr;
+    auto t0 = std::chrono::steady_clock::now();
+    pbc_jk *h = nullptr;
+    int rc = pbcjk::handle_new(cell, atoms, basis, omega, thr, &h);
+    if (rc) return rc;
+    rc = pbcjk::handle_device(h, nullptr, true, 0.0);
+    if (rc) {
+        std::string keep = g_err;
+        pbcjk::handle_delete(h);
+        g_err = keep;
+        return rc;
+    }
     h->st.t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     *out = h;
     return 0;
@@ -520,19 +704,22 @@ int pbc_jk_build(pbc_jk *h, const double *D, double *J, double *K, double *E_J, 
     return 0;
 }
 
-void pbc_jk_destroy(pbc_jk *h)
-{
-    if (!h) return;
-    (void)hipSetDevice(h->device);
-    if (h->own) (void)hipStreamSynchronize(h->own);
-    release(h);
-    delete h;
-}
+void pbc_jk_destroy(pbc_jk *h) { pbcjk::handle_delete(h); }
 
 int pbc_jk_nbf(const pbc_jk *h)
 {
     if (!h) return fail(PBC_JK_EINVAL, "handle is NULL");
     return h->S.nbf;
+}
+
+int pbc_jk_set_lr(pbc_jk *h, int mode, double tol)
+{
+    if (!h) return fail(PBC_JK_EINVAL, "handle is NULL");
+    if (mode != PBC_JK_LR_AUTO && mode != PBC_JK_LR_DENSE) return fail(PBC_JK_EINVAL, "unknown reciprocal exchange mode");
+    if (!(tol < 1.0)) return fail(PBC_JK_EINVAL, "tolerance must be below 1");
+    h->lr_mode = mode;
+    if (tol > 0.0) h->lr_tol = tol;
+    return 0;
 }
 
 int pbc_jk_set_parts(pbc_jk *h, int mask)
@@ -561,17 +748,24 @@ int pbc_jk_stats(const pbc_jk *hc, pbc_jk_counters *out)
         h->st.terms = (double)cnt[1];
         h->st.terms_fp32 = (double)cnt[23];
         for (int k = 0; k < 21; ++k) h->st.terms_class[k] = (double)cnt[2 + k];
-        h->st.t_gemm_ms = h->st.t_sfac_ms = h->st.gemm_flops = 0.0;
+        int ctl[4] = {0, 1, 0, 0};
+        if (h->lr_ran) HIPCHK(hipMemcpy(ctl, h->d_ctl, sizeof ctl, hipMemcpyDeviceToHost));
+        const bool dense = !h->lr_ran || ctl[1];
+        h->st.lr_rank = dense ? -1.0 : (double)ctl[0];
+        h->st.t_gemm_ms = h->st.t_sfac_ms = h->st.gemm_flops = h->st.t_chol_ms = 0.0;
         h->st.n_gemm = 0;
         for (int i = 0; i < h->ntimed; ++i) {
             float ms = 0;
             HIPCHK(hipEventElapsedTime(&ms, h->tev[2 * i], h->tev[2 * i + 1]));
-            if (h->tkind[i] == 0) {
+            const int kind = h->tkind[i];
+            if (kind == 0 || (kind == 2 && !dense) || (kind == 3 && dense)) {
                 h->st.t_gemm_ms += ms;
-                h->st.gemm_flops += h->tflops[i];
+                h->st.gemm_flops += h->tflops[i] * (kind == 2 ? (double)ctl[0] : 1.0);
                 h->st.n_gemm++;
-            } else {
+            } else if (kind == 1) {
                 h->st.t_sfac_ms += ms;
+            } else if (kind == 4) {
+                h->st.t_chol_ms += ms;
             }
         }
     }

@@ -82,8 +82,31 @@ struct GemmArgs {
     double alpha0;        // scalar factor applied on top
     int reduce;
     int slices;
+    int transA;           // A element (m, k) read from A[k * lda + m]
+    int transB;           // B element (k, j) read from B[j * ldb + k]
+    int upper;            // compute only output tiles on or above the diagonal (M == N)
+    // Device-side gating by the low-rank control block ctl = {rank, use_dense}:
+    // 0 none; 1 skip if use_dense, N = rank; 2 skip if use_dense, K = rank;
+    // 3 skip unless use_dense.
+    const int *ctl;
+    int ctl_mode;
 };
 hipError_t launch_dgemm(const GemmArgs &a, hipStream_t st);
+constexpr int kGemmTile = 128;   // output tile edge of launch_dgemm
+
+// Pivoted Cholesky of a symmetric n x n matrix D ~= L L^T, L stored by
+// columns (column j at L + j * n), run as one launch per column so that the
+// rank never leaves the device.  Stops when the largest remaining diagonal
+// entry is <= tol * max diag(D) or after rmax columns.  ctl (4 ints):
+// {rank, use_dense, done, -}.  work: n + 2 * ceil(n / 64) + 4 doubles and
+// 2 * ceil(n / 64) ints (wi).  use_dense is set when the factor did not
+// converge within rmax columns or D has a diagonal entry below -tol * max.
+hipError_t launch_pchol(const double *D, int n, double tol, int rmax, double *L, double *work, int *wi,
+                        int *ctl, hipStream_t st);
+// After R = L L^T: sets ctl[1] when max |D - R| exceeds 2 tol max diag(D)
+// plus the rounding allowance 4 n eps max diag(D).
+hipError_t launch_lowrank_check(const double *D, const double *R, int n, const double *work, int *ctl,
+                                hipStream_t st);
 
 hipError_t launch_fill(double *p, long n, double v, hipStream_t st);
 
@@ -113,6 +136,7 @@ hipError_t launch_axpy_scaled(double *Y, const double *X, long n, double f, cons
 struct FinalArgs {
     const double *X, *Jt;
     int nbfc, nbf;
+    int jt_upper;          // Jt holds only the upper output tiles of launch_dgemm
     const int *inv_ci;     // 3 * nbf scaled-Cartesian indices (-1 = none)
     const double *inv_cc;  // 3 * nbf coefficients
     double *out;           // nbf^2

@@ -10,6 +10,8 @@
 // K_LR is a dense contraction and runs on the FP64 matrix cores.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device_math.h"
 #include "kernels.h"
 
@@ -239,7 +241,9 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs a)
         for (int v = 0; v < 3; ++v) {
             int j = a.inv_ci[3 * q + v];
             if (j < 0) continue;
-            double x = a.X[(long)i * nc + j] + a.X[(long)j * nc + i] + a.Jt[(long)i * nc + j];
+            long jt = (long)i * nc + j;
+            if (a.jt_upper && i / kGemmTile > j / kGemmTile) jt = (long)j * nc + i;
+            double x = a.X[(long)i * nc + j] + a.X[(long)j * nc + i] + a.Jt[jt];
             s += a.inv_cc[3 * p + u] * a.inv_cc[3 * q + v] * x;
         }
     }
@@ -258,7 +262,16 @@ __global__ __launch_bounds__(256) void k_dgemm(GemmArgs g)
 {
     __shared__ double As[GBK][GBM + GPAD];
     __shared__ double Bs[GBK][GBN + GPAD];
+    if (g.upper && blockIdx.y > blockIdx.x) return;
+    int N = g.N, K = g.K;
+    if (g.ctl_mode) {
+        const int use_dense = g.ctl[1];
+        if (g.ctl_mode == 3 ? !use_dense : use_dense) return;
+        if (g.ctl_mode == 1) N = g.ctl[0];
+        if (g.ctl_mode == 2) K = g.ctl[0];
+    }
     const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
+    if (n0 >= N) return;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int wm = wave >> 1, wn = wave & 1;
     const int lr = lane & 15, lk = lane >> 4;
@@ -280,34 +293,64 @@ __global__ __launch_bounds__(256) void k_dgemm(GemmArgs g)
     // each thread stages 8 A values (one row, 8 consecutive k) and 8 B values
     const int am = tid >> 1, ak = (tid & 1) * 8;
     const int bk = tid >> 4, bn = (tid & 15) * 8;
+    const int tn = tid >> 1, tk = (tid & 1) * 8;   // transposed B staging
+    const int tam = (tid & 15) * 8, tak = tid >> 4; // transposed A staging
     double ra[8], rb[8];
-    const int nk = (g.K + GBK - 1) / GBK;
+    const int nk = (K + GBK - 1) / GBK;
     for (int b = b0; b < b1; ++b) {
         const double *A = g.A + (long)b * g.sA;
         const double *B = g.B + (long)b * g.sB;
         const double alpha = (g.alpha ? g.alpha[b] : 1.0) * g.alpha0;
         auto load = [&](int kt) {
             const int k0 = kt * GBK;
-            const int gm = m0 + am;
+            if (g.transA) {
+                const int gk = k0 + tak;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                int gk = k0 + ak + u;
-                ra[u] = (gm < g.M && gk < g.K) ? A[(long)gm * g.lda + gk] : 0.0;
+                for (int u = 0; u < 8; ++u) {
+                    int gm = m0 + tam + u;
+                    ra[u] = (gm < g.M && gk < K) ? A[(long)gk * g.lda + gm] : 0.0;
+                }
+            } else {
+                const int gm = m0 + am;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    int gk = k0 + ak + u;
+                    ra[u] = (gm < g.M && gk < K) ? A[(long)gm * g.lda + gk] : 0.0;
+                }
             }
-            const int gk = k0 + bk;
+            if (g.transB) {
+                const int gn = n0 + tn;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                int gn = n0 + bn + u;
-                rb[u] = (gk < g.K && gn < g.N) ? B[(long)gk * g.ldb + gn] : 0.0;
+                for (int u = 0; u < 8; ++u) {
+                    int gk2 = k0 + tk + u;
+                    rb[u] = (gk2 < K && gn < N) ? B[(long)gn * g.ldb + gk2] : 0.0;
+                }
+            } else {
+                const int gk = k0 + bk;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    int gn = n0 + bn + u;
+                    rb[u] = (gk < K && gn < N) ? B[(long)gk * g.ldb + gn] : 0.0;
+                }
             }
         };
         load(0);
         for (int kt = 0; kt < nk; ++kt) {
             __syncthreads();
+            if (g.transA) {
 #pragma unroll
-            for (int u = 0; u < 8; ++u) As[ak + u][am] = alpha * ra[u];
+                for (int u = 0; u < 8; ++u) As[tak][tam + u] = alpha * ra[u];
+            } else {
 #pragma unroll
-            for (int u = 0; u < 8; ++u) Bs[bk][bn + u] = rb[u];
+                for (int u = 0; u < 8; ++u) As[ak + u][am] = alpha * ra[u];
+            }
+            if (g.transB) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) Bs[tk + u][tn] = rb[u];
+            } else {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) Bs[bk][bn + u] = rb[u];
+            }
             __syncthreads();
             if (kt + 1 < nk) load(kt + 1);
 #pragma unroll
@@ -334,7 +377,7 @@ __global__ __launch_bounds__(256) void k_dgemm(GemmArgs g)
                     for (int r = 0; r < 4; ++r) {
                         int gm = m0 + wm * 64 + i * 16 + lk + 4 * r;
                         int gn = n0 + wn * 64 + j * 16 + lr;
-                        if (gm < g.M && gn < g.N) C[(long)gm * g.ldc + gn] = acc[i][j][r];
+                        if (gm < g.M && gn < N) C[(long)gm * g.ldc + gn] = acc[i][j][r];
                     }
         }
     }
@@ -347,12 +390,272 @@ __global__ __launch_bounds__(256) void k_dgemm(GemmArgs g)
                 for (int r = 0; r < 4; ++r) {
                     int gm = m0 + wm * 64 + i * 16 + lk + 4 * r;
                     int gn = n0 + wn * 64 + j * 16 + lr;
-                    if (gm < g.M && gn < g.N) atomicAdd(&g.C[(long)gm * g.ldc + gn], acc[i][j][r]);
+                    if (gm < g.M && gn < N) atomicAdd(&g.C[(long)gm * g.ldc + gn], acc[i][j][r]);
                 }
     }
 }
 
+// ---------------------------------------------------------------- pivoted Cholesky
+// Step k: every block reduces the per-block maxima of the remaining diagonal
+// left by step k - 1 to the pivot p, then forms rows [64 b, 64 b + 64) of
+// column k, L_ik = (D_ip - sum_{j<k} L_ij L_pj) / sqrt(d_p), and the new
+// remaining diagonal d_i -= L_ik^2, with its block maximum for step k + 1.
+// Work layout: diag[n] | pv[2][nblk] | stop, max0; wi: pi[2][nblk].
+constexpr int kCholRows = 64;
+constexpr int kCholSingleMax = 2048;   // one-workgroup factorisation up to this n
+
+__device__ inline void argmax_merge(double &v, int &i, double ov, int oi)
+{
+    if (ov > v || (ov == v && oi < i)) { v = ov; i = oi; }
+}
+
+__global__ __launch_bounds__(1024) void k_pchol_init(const double *D, int n, double tol, double *work, int *wi,
+                                                    int *ctl)
+{
+    __shared__ double sm[16], sn[16];
+    const int nblk = (n + kCholRows - 1) / kCholRows;
+    double *diag = work, *pv = work + n, *par = work + n + 2 * nblk;
+    int *pi = wi;
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, nw = blockDim.x >> 6;
+    double mx = 0.0, mn = 0.0;
+    for (int i = tid; i < n; i += blockDim.x) {
+        const double d = D[(long)i * n + i];
+        diag[i] = d;
+        mx = fmax(mx, d);
+        mn = fmin(mn, d);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        mx = fmax(mx, __shfl_xor(mx, off, 64));
+        mn = fmin(mn, __shfl_xor(mn, off, 64));
+    }
+    if (l == 0) { sm[w] = mx; sn[w] = mn; }
+    __syncthreads();
+    mx = 0.0; mn = 0.0;
+    for (int u = 0; u < nw; ++u) { mx = fmax(mx, sm[u]); mn = fmin(mn, sn[u]); }
+    // block maxima of the diagonal for step 0
+    for (int b = w; b < nblk; b += nw) {
+        const int i = b * kCholRows + l;
+        double v = i < n ? diag[i] : -1e300;
+        int ii = i;
+        for (int off = 32; off > 0; off >>= 1) argmax_merge(v, ii, __shfl_xor(v, off, 64), __shfl_xor(ii, off, 64));
+        if (l == 0) { pv[b] = v; pi[b] = ii; }
+    }
+    if (tid == 0) {
+        par[0] = tol * mx;
+        par[1] = mx;
+        ctl[0] = 0;
+        ctl[1] = (mn < -tol * mx) ? 1 : 0;
+        ctl[2] = (mx > 0.0) ? 0 : 1;
+        ctl[3] = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_pchol_step(const double *D, int n, int k, double *L, double *work, int *wi,
+                                                   int *ctl)
+{
+    __shared__ double sred[4][kCholRows];
+    __shared__ double s_piv;
+    __shared__ int s_p, s_done;
+    if (threadIdx.x == 0) s_done = ctl[2];
+    __syncthreads();
+    if (s_done) return;
+    const int nblk = (n + kCholRows - 1) / kCholRows;
+    double *diag = work, *par = work + n + 2 * nblk;
+    const double *pv_in = work + n + (k & 1) * nblk;
+    double *pv_out = work + n + ((k + 1) & 1) * nblk;
+    const int *pi_in = wi + (k & 1) * nblk;
+    int *pi_out = wi + ((k + 1) & 1) * nblk;
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    if (w == 0) {
+        double v = -1e300;
+        int ii = 0x7fffffff;
+        for (int b = l; b < nblk; b += 64) argmax_merge(v, ii, pv_in[b], pi_in[b]);
+        for (int off = 32; off > 0; off >>= 1) argmax_merge(v, ii, __shfl_xor(v, off, 64), __shfl_xor(ii, off, 64));
+        if (l == 0) { s_piv = v; s_p = ii; }
+    }
+    __syncthreads();
+    const double piv = s_piv;
+    const int p = s_p;
+    if (!(piv > par[0])) {
+        if (blockIdx.x == 0 && tid == 0) { ctl[0] = k; ctl[2] = 1; }
+        return;
+    }
+    const int i = blockIdx.x * kCholRows + l;
+    double s = 0.0;
+    if (i < n)
+        for (int j = w; j < k; j += 4) s += L[(long)j * n + i] * L[(long)j * n + p];
+    sred[w][l] = s;
+    __syncthreads();
+    if (w == 0) {
+        double v = -1e300;
+        if (i < n) {
+            const double x = (D[(long)p * n + i] - (sred[0][l] + sred[1][l] + sred[2][l] + sred[3][l])) / sqrt(piv);
+            L[(long)k * n + i] = x;
+            const double d = (i == p) ? 0.0 : diag[i] - x * x;
+            diag[i] = d;
+            v = d;
+        }
+        int ii = i;
+        for (int off = 32; off > 0; off >>= 1) argmax_merge(v, ii, __shfl_xor(v, off, 64), __shfl_xor(ii, off, 64));
+        if (l == 0) { pv_out[blockIdx.x] = v; pi_out[blockIdx.x] = ii; }
+    }
+}
+
+// After the last step: rank = rmax when the factor did not stop by itself;
+// use_dense when it did not converge or a remaining diagonal entry is below
+// -tol * max diag.
+__global__ __launch_bounds__(256) void k_pchol_fin(int n, int rmax, const double *work, const int *wi, int *ctl)
+{
+    __shared__ int s_bad;
+    const int nblk = (n + kCholRows - 1) / kCholRows;
+    const double *diag = work, *par = work + n + 2 * nblk;
+    const double stop = par[0];
+    if (threadIdx.x == 0) s_bad = 0;
+    __syncthreads();
+    const bool done = ctl[2] != 0;
+    int bad = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double d = diag[i];
+        if (d < -stop || (!done && d > stop)) bad = 1;
+    }
+    if (bad) atomicOr(&s_bad, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (!done) { ctl[0] = rmax; ctl[2] = 1; }
+        if (s_bad) ctl[1] = 1;
+    }
+}
+
+// The whole factorisation in one workgroup (for small n, where one launch per
+// column would be launch-bound).  Same outputs as init + steps + fin.
+__global__ __launch_bounds__(1024) void k_pchol_single(const double *D, int n, double tol, int rmax, double *L,
+                                                      double *work, int *ctl)
+{
+    __shared__ double sv[16];
+    __shared__ int si[16];
+    __shared__ double s_mx, s_mn, s_piv;
+    __shared__ int s_p, s_bad;
+    const int nblk = (n + kCholRows - 1) / kCholRows;
+    double *diag = work, *par = work + n + 2 * nblk;
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, nw = blockDim.x >> 6;
+    double mx = 0.0, mn = 0.0;
+    for (int i = tid; i < n; i += blockDim.x) {
+        const double d = D[(long)i * n + i];
+        diag[i] = d;
+        mx = fmax(mx, d);
+        mn = fmin(mn, d);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        mx = fmax(mx, __shfl_xor(mx, off, 64));
+        mn = fmin(mn, __shfl_xor(mn, off, 64));
+    }
+    if (l == 0) sv[w] = mx;
+    __syncthreads();
+    if (tid == 0) {
+        double a = 0.0;
+        for (int u = 0; u < nw; ++u) a = fmax(a, sv[u]);
+        s_mx = a;
+        s_bad = 0;
+    }
+    __syncthreads();
+    if (l == 0) sv[w] = mn;
+    __syncthreads();
+    if (tid == 0) {
+        double b = 0.0;
+        for (int u = 0; u < nw; ++u) b = fmin(b, sv[u]);
+        s_mn = b;
+    }
+    __syncthreads();
+    const double max0 = s_mx, stop = tol * max0;
+    int k = 0;
+    bool stopped = !(max0 > 0.0);
+    for (; k < rmax && !stopped; ++k) {
+        double bv = -1e300;
+        int bi = 0x7fffffff;
+        for (int i = tid; i < n; i += blockDim.x) argmax_merge(bv, bi, diag[i], i);
+        for (int off = 32; off > 0; off >>= 1) argmax_merge(bv, bi, __shfl_xor(bv, off, 64), __shfl_xor(bi, off, 64));
+        if (l == 0) { sv[w] = bv; si[w] = bi; }
+        __syncthreads();
+        if (tid == 0) {
+            double t = sv[0];
+            int ti = si[0];
+            for (int u = 1; u < nw; ++u) argmax_merge(t, ti, sv[u], si[u]);
+            s_piv = t;
+            s_p = ti;
+        }
+        __syncthreads();
+        const double piv = s_piv;
+        const int p = s_p;
+        if (!(piv > stop)) {
+            stopped = true;
+            break;
+        }
+        const double inv = 1.0 / sqrt(piv);
+        for (int i = tid; i < n; i += blockDim.x) {
+            double v = D[(long)p * n + i];
+            for (int j = 0; j < k; ++j) v -= L[(long)j * n + i] * L[(long)j * n + p];
+            v *= inv;
+            L[(long)k * n + i] = v;
+            diag[i] = (i == p) ? 0.0 : diag[i] - v * v;
+        }
+        __syncthreads();
+    }
+    int bad = 0;
+    for (int i = tid; i < n; i += blockDim.x) {
+        const double d = diag[i];
+        if (d < -stop || (!stopped && d > stop)) bad = 1;
+    }
+    if (bad) atomicOr(&s_bad, 1);
+    __syncthreads();
+    if (tid == 0) {
+        par[0] = stop;
+        par[1] = max0;
+        ctl[0] = k;
+        ctl[1] = (s_bad || s_mn < -stop) ? 1 : 0;
+        ctl[2] = 1;
+        ctl[3] = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_lowrank_check(const double *D, const double *R, int n, const double *work,
+                                                      int *ctl)
+{
+    if (ctl[1]) return;
+    const int nblk = (n + kCholRows - 1) / kCholRows;
+    const double *par = work + n + 2 * nblk;
+    const double thr = 2.0 * par[0] + 4.0 * n * 2.220446049250313e-16 * par[1];
+    const long n2 = (long)n * n;
+    int bad = 0;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n2; e += (long)gridDim.x * blockDim.x)
+        if (!(fabs(D[e] - R[e]) <= thr)) bad = 1;
+    if (bad) atomicOr(&ctl[1], 1);
+}
+
 }  // namespace
+
+hipError_t launch_pchol(const double *D, int n, double tol, int rmax, double *L, double *work, int *wi,
+                        int *ctl, hipStream_t st)
+{
+    const int nblk = (n + kCholRows - 1) / kCholRows;
+    if (n <= kCholSingleMax) {
+        hipLaunchKernelGGL(k_pchol_single, dim3(1), dim3(1024), 0, st, D, n, tol, rmax, L, work, ctl);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_pchol_init, dim3(1), dim3(1024), 0, st, D, n, tol, work, wi, ctl);
+    for (int k = 0; k < rmax; ++k)
+        hipLaunchKernelGGL(k_pchol_step, dim3(nblk), dim3(256), 0, st, D, n, k, L, work, wi, ctl);
+    hipLaunchKernelGGL(k_pchol_fin, dim3(1), dim3(256), 0, st, n, rmax, (const double *)work, (const int *)wi, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_lowrank_check(const double *D, const double *R, int n, const double *work, int *ctl,
+                                hipStream_t st)
+{
+    const long n2 = (long)n * n;
+    const unsigned blocks = (unsigned)std::min<long>(2048, (n2 + 255) / 256);
+    hipLaunchKernelGGL(k_lowrank_check, dim3(std::max(1u, blocks)), dim3(256), 0, st, D, R, n, work, ctl);
+    return hipGetLastError();
+}
 
 hipError_t launch_sfac(int cls, const SfacArgs &a, hipStream_t st)
 {

@@ -20,11 +20,16 @@ PBC_JK_EINVAL = -1
 PBC_JK_ENOMEM = -2
 PBC_JK_EDEVICE = -3
 PBC_JK_ENOTSUP = -4
+PBC_JK_ECANCELED = -5
+PBC_JK_EBUSY = -6
 PART_SR, PART_LR, PART_SELF = 1, 2, 4
+LR_AUTO, LR_DENSE = 0, 1
 
 # every symbol the header declares
 EXPORTS = ["pbc_jk_create", "pbc_jk_build", "pbc_jk_build_device", "pbc_jk_destroy",
-           "pbc_jk_nbf", "pbc_jk_stats", "pbc_jk_set_parts", "pbc_jk_last_error"]
+           "pbc_jk_nbf", "pbc_jk_stats", "pbc_jk_set_parts", "pbc_jk_set_lr", "pbc_jk_last_error",
+           "pbc_jk_server_create", "pbc_jk_server_submit", "pbc_jk_server_wait", "pbc_jk_server_cancel",
+           "pbc_jk_server_stats", "pbc_jk_server_destroy"]
 
 
 class pbc_cell(ctypes.Structure):
@@ -54,7 +59,25 @@ class pbc_jk_counters(ctypes.Structure):
                 ("t_build_ms", c_double), ("t_sr_ms", c_double), ("t_lr_ms", c_double),
                 ("t_other_ms", c_double), ("t_gemm_ms", c_double), ("gemm_flops", c_double),
                 ("n_gemm", c_int), ("t_sfac_ms", c_double), ("terms_class", c_double * 21),
-                ("n_group_pairs", c_double)]
+                ("n_group_pairs", c_double), ("lr_rank", c_double), ("t_chol_ms", c_double)]
+
+
+class pbc_jk_server_config(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("slots", c_int), ("cache_cells", c_int),
+                ("lr_budget_mb", c_double)]
+
+
+class pbc_jk_request_info(ctypes.Structure):
+    _fields_ = [("status", c_int), ("cache_hit", c_int), ("retries", c_int), ("nbf", c_int),
+                ("queue_ms", c_double), ("setup_ms", c_double), ("build_ms", c_double),
+                ("latency_ms", c_double), ("device_bytes", ctypes.c_size_t), ("error", ctypes.c_char * 160)]
+
+
+class pbc_jk_server_counters(ctypes.Structure):
+    _fields_ = [("submitted", c_long), ("completed", c_long), ("failed", c_long), ("cancelled", c_long),
+                ("cache_hits", c_long), ("evictions", c_long), ("retries", c_long), ("slots", c_int),
+                ("peak_running", c_int), ("budget", ctypes.c_size_t), ("in_use", ctypes.c_size_t),
+                ("peak_in_use", ctypes.c_size_t)]
 
 
 class PbcJkError(RuntimeError):
@@ -91,6 +114,23 @@ def load():
     lib.pbc_jk_stats.restype = c_int
     lib.pbc_jk_set_parts.argtypes = [c_void_p, c_int]
     lib.pbc_jk_set_parts.restype = c_int
+    lib.pbc_jk_set_lr.argtypes = [c_void_p, c_int, c_double]
+    lib.pbc_jk_set_lr.restype = c_int
+    lib.pbc_jk_server_create.argtypes = [POINTER(pbc_jk_server_config), POINTER(c_void_p)]
+    lib.pbc_jk_server_create.restype = c_int
+    lib.pbc_jk_server_submit.argtypes = [c_void_p, POINTER(pbc_cell), POINTER(pbc_atoms), POINTER(pbc_basis),
+                                         c_double, POINTER(pbc_jk_thresholds), POINTER(c_double),
+                                         POINTER(c_double), POINTER(c_double), POINTER(c_double),
+                                         POINTER(c_double), POINTER(ctypes.c_ulonglong)]
+    lib.pbc_jk_server_submit.restype = c_int
+    lib.pbc_jk_server_wait.argtypes = [c_void_p, ctypes.c_ulonglong, POINTER(pbc_jk_request_info)]
+    lib.pbc_jk_server_wait.restype = c_int
+    lib.pbc_jk_server_cancel.argtypes = [c_void_p, ctypes.c_ulonglong]
+    lib.pbc_jk_server_cancel.restype = c_int
+    lib.pbc_jk_server_stats.argtypes = [c_void_p, POINTER(pbc_jk_server_counters)]
+    lib.pbc_jk_server_stats.restype = c_int
+    lib.pbc_jk_server_destroy.argtypes = [c_void_p]
+    lib.pbc_jk_server_destroy.restype = None
     lib.pbc_jk_last_error.argtypes = []
     lib.pbc_jk_last_error.restype = c_char_p
     _lib = lib
@@ -114,10 +154,8 @@ def _ip(a):
     return a.ctypes.data_as(POINTER(c_int))
 
 
-def pbc_jk_create(cell, xyz, shell_atom, shell_l, shell_pure, shell_nprim, exps, coefs,
-                  omega: float, thr=None) -> int:
-    """Returns the opaque handle (an integer address)."""
-    lib = load()
+def _inputs(cell, xyz, shell_atom, shell_l, shell_pure, shell_nprim, exps, coefs, thr):
+    """C structs for one cell; `keep` owns the arrays the structs point into."""
     c = pbc_cell()
     c.a[:] = [float(x) for x in np.asarray(cell, dtype=np.float64).ravel()]
     keep = [np.ascontiguousarray(xyz, dtype=np.float64),
@@ -134,6 +172,14 @@ def pbc_jk_create(cell, xyz, shell_atom, shell_l, shell_pure, shell_nprim, exps,
     if thr is not None:
         th = pbc_jk_thresholds(thr.pair_R, thr.pair_cs, thr.ewald_R, thr.ewald_K, thr.schwarz,
                                thr.fp32_below, thr.r_cut, thr.g_cut)
+    return c, at, bs, th, keep
+
+
+def pbc_jk_create(cell, xyz, shell_atom, shell_l, shell_pure, shell_nprim, exps, coefs,
+                  omega: float, thr=None) -> int:
+    """Returns the opaque handle (an integer address)."""
+    lib = load()
+    c, at, bs, th, keep = _inputs(cell, xyz, shell_atom, shell_l, shell_pure, shell_nprim, exps, coefs, thr)
     h = c_void_p()
     rc = lib.pbc_jk_create(byref(c), byref(at), byref(bs), float(omega),
                            byref(th) if th is not None else None, byref(h))
@@ -195,6 +241,10 @@ def pbc_jk_set_parts(h: int, mask: int):
     _check(load().pbc_jk_set_parts(c_void_p(h), int(mask)))
 
 
+def pbc_jk_set_lr(h: int, mode: int, tol: float = 0.0):
+    _check(load().pbc_jk_set_lr(c_void_p(h), int(mode), float(tol)))
+
+
 class Handle:
     """Owns one library handle for a System from paper_2410_22278_amd.inputs."""
 
@@ -217,10 +267,81 @@ class Handle:
     def set_parts(self, mask):
         pbc_jk_set_parts(self.h, mask)
 
+    def set_lr(self, mode, tol=0.0):
+        pbc_jk_set_lr(self.h, mode, tol)
+
     def close(self):
         if self.h:
             pbc_jk_destroy(self.h)
             self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """The library's request server (pbc_jk_server_*): submit builds for any
+    System, wait for them in any order.  Output arrays are owned here until
+    the ticket is waited for."""
+
+    def __init__(self, hbm_budget: int = 0, slots: int = 4, cache_cells: bool = True,
+                 lr_budget_mb: float = 0.0):
+        lib = load()
+        cfg = pbc_jk_server_config(int(hbm_budget), int(slots), 1 if cache_cells else 0, float(lr_budget_mb))
+        s = c_void_p()
+        _check(lib.pbc_jk_server_create(byref(cfg), byref(s)))
+        self.s = s.value
+        self._live = {}
+
+    def submit(self, system, D=None, want_J=True, want_K=True) -> int:
+        lib = load()
+        c, at, bs, th, keep = _inputs(system.cell, system.xyz, system.shell_atom, system.shell_l,
+                                      system.shell_pure, system.shell_nprim, system.exps, system.coefs,
+                                      system.thr)
+        D = np.ascontiguousarray(system.D if D is None else D, dtype=np.float64)
+        n = D.shape[0]
+        J = np.empty((n, n)) if want_J else None
+        K = np.empty((n, n)) if want_K else None
+        ej, ek = c_double(), c_double()
+        t = ctypes.c_ulonglong()
+        rc = lib.pbc_jk_server_submit(c_void_p(self.s), byref(c), byref(at), byref(bs), float(system.omega),
+                                      byref(th), _dp(D), _dp(J) if J is not None else None,
+                                      _dp(K) if K is not None else None, byref(ej), byref(ek), byref(t))
+        _check(rc)
+        self._live[t.value] = (J, K, ej, ek)
+        return t.value
+
+    def wait(self, ticket: int) -> dict:
+        """Returns {"status", "J", "K", "E_J", "E_K", and the request info}."""
+        info = pbc_jk_request_info()
+        rc = load().pbc_jk_server_wait(c_void_p(self.s), ctypes.c_ulonglong(ticket), byref(info))
+        J, K, ej, ek = self._live.pop(ticket, (None, None, c_double(), c_double()))
+        out = {k: getattr(info, k) for k, _ in info._fields_ if k != "error"}
+        out.update(status=rc, error=info.error.decode(errors="replace"), J=J, K=K, E_J=ej.value, E_K=ek.value)
+        return out
+
+    def cancel(self, ticket: int) -> int:
+        return load().pbc_jk_server_cancel(c_void_p(self.s), ctypes.c_ulonglong(ticket))
+
+    def stats(self) -> dict:
+        c = pbc_jk_server_counters()
+        _check(load().pbc_jk_server_stats(c_void_p(self.s), byref(c)))
+        return {k: getattr(c, k) for k, _ in c._fields_}
+
+    def close(self):
+        if getattr(self, "s", None):
+            load().pbc_jk_server_destroy(c_void_p(self.s))
+            self.s = None
+            self._live.clear()
 
     def __enter__(self):
         return self
