@@ -19,6 +19,9 @@ using namespace pbcjk;
 namespace {
 
 constexpr int kClassL[kNumClass] = {0, 1, 2, 2, 3, 4};
+constexpr int kNumCounters = 48;     // see SRArgs::counters
+constexpr double kFoldRmin = 20.0;   // bohr: cells with a shorter lattice vector start folded
+constexpr double kFoldRatio = 1.5;   // shifts per quartet above which the lattice sum is folded
 
 thread_local std::string g_err;
 
@@ -70,6 +73,16 @@ struct pbc_jk {
     bool lr_ran = false;
     size_t nbr_bytes_needed = 0;   // set once the neighbour lists are counted
     long nbr_off[22] = {0};
+    // per-build work lists (density-screened neighbour lists, FP64 and FP32)
+    // at the same offsets, and their lengths (2 per class pair)
+    int *d_w64b = nullptr, *d_w64k = nullptr, *d_w32b = nullptr, *d_w32k = nullptr;
+    unsigned long long *d_wcnt = nullptr;
+    unsigned long long *d_ncnt = nullptr;   // neighbour-list segment lengths (21)
+    // counters of the last finished build (pinned copy, event-guarded), used
+    // to choose per class pair whether the lattice sum is folded into R_{tuv}
+    unsigned long long *h_cnt = nullptr;
+    hipEvent_t ev_cnt = nullptr;
+    bool fold[21] = {false};
     int gchunk = 0;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     // event pairs around GEMM and structure-factor launches of one build
@@ -143,7 +156,8 @@ void release_device(pbc_jk *h)
                    (void **)&h->d_T, (void **)&h->d_rho, (void **)&h->d_scal, (void **)&h->d_Jo,
                    (void **)&h->d_Ko, (void **)&h->d_dmaxg, (void **)&h->d_cnt, (void **)&h->d_nbr_bra,
                    (void **)&h->d_nbr_ket, (void **)&h->d_L, (void **)&h->d_pw, (void **)&h->d_pwi,
-                   (void **)&h->d_ctl};
+                   (void **)&h->d_ctl, (void **)&h->d_w64b, (void **)&h->d_w64k, (void **)&h->d_w32b,
+                   (void **)&h->d_w32k, (void **)&h->d_wcnt, (void **)&h->d_ncnt};
     for (void **p : pp) {
         dfree(h, *p);
         *p = nullptr;
@@ -159,6 +173,10 @@ void release(pbc_jk *h)
         if (e) (void)hipEventDestroy(e);
     for (auto &e : h->tev)
         if (e) (void)hipEventDestroy(e);
+    if (h->ev_cnt) (void)hipEventDestroy(h->ev_cnt);
+    h->ev_cnt = nullptr;
+    if (h->h_cnt) (void)hipHostFree(h->h_cnt);
+    h->h_cnt = nullptr;
     if (h->own) (void)hipStreamDestroy(h->own);
     h->own = nullptr;
     for (auto &e : h->ev) e = nullptr;
@@ -246,7 +264,14 @@ int create_device(pbc_jk *h)
     if ((rc = dalloc(h, &h->d_Ko, m2))) return rc;
     if ((rc = dalloc(h, &h->d_scal, 4))) return rc;
     if ((rc = dalloc(h, &h->d_dmaxg, 1))) return rc;
-    if ((rc = dalloc(h, &h->d_cnt, 32))) return rc;
+    if ((rc = dalloc(h, &h->d_cnt, kNumCounters))) return rc;
+    if (!h->dry) {
+        if (!h->h_cnt) HIPCHK(hipHostMalloc((void **)&h->h_cnt, kNumCounters * sizeof(unsigned long long)));
+        std::memset(h->h_cnt, 0, kNumCounters * sizeof(unsigned long long));
+        if (!h->ev_cnt) HIPCHK(hipEventCreateWithFlags(&h->ev_cnt, hipEventDisableTiming));
+        // first guess: quartets of small cells have several lattice shifts
+        for (bool &f : h->fold) f = S.lat.Rmin < kFoldRmin;
+    }
     // reciprocal-space chunk: F and T hold 2 * gchunk matrices each
     const int nG = (int)S.Gw.size();
     double budget_mb = h->lr_budget_mb > 0 ? h->lr_budget_mb : 16384.0;
@@ -318,9 +343,15 @@ int build_neighbours(pbc_jk *h)
             for (int i = 0; i < a.nb; ++i) { offs[slot][i] = total; total += cnt[i]; }
         }
     h->nbr_off[21] = total;
-    h->nbr_bytes_needed = 2 * Arena::round_up(sizeof(int) * (size_t)std::max(1L, total));
-    if ((rc = dalloc(h, &h->d_nbr_bra, (size_t)std::max(1L, total))) ||
-        (rc = dalloc(h, &h->d_nbr_ket, (size_t)std::max(1L, total))))
+    // the FP64/FP32 work lists exist only with mixed precision
+    const size_t ne = (size_t)std::max(1L, total), nw = S.fp32_below > 0 ? ne : 1;
+    h->nbr_bytes_needed = 2 * Arena::round_up(sizeof(int) * ne) + 4 * Arena::round_up(sizeof(int) * nw) +
+                          Arena::round_up(42 * sizeof(unsigned long long)) +
+                          Arena::round_up(21 * sizeof(unsigned long long));
+    if ((rc = dalloc(h, &h->d_nbr_bra, ne)) || (rc = dalloc(h, &h->d_nbr_ket, ne)) ||
+        (rc = dalloc(h, &h->d_w64b, nw)) || (rc = dalloc(h, &h->d_w64k, nw)) ||
+        (rc = dalloc(h, &h->d_w32b, nw)) || (rc = dalloc(h, &h->d_w32k, nw)) ||
+        (rc = dalloc(h, &h->d_wcnt, 42)) || (rc = dalloc(h, &h->d_ncnt, 21)))
         return rc;
     slot = 0;
     for (int cb = 0; cb < kNumClass; ++cb)
@@ -335,6 +366,9 @@ int build_neighbours(pbc_jk *h)
             HIPCHK(hipStreamSynchronize(st));
         }
     h->st.n_group_pairs = (double)total;
+    unsigned long long seg[21];
+    for (int k = 0; k < 21; ++k) seg[k] = (unsigned long long)(h->nbr_off[k + 1] - h->nbr_off[k]);
+    HIPCHK(hipMemcpy(h->d_ncnt, seg, sizeof seg, hipMemcpyHostToDevice));
     return 0;
 }
 
@@ -358,10 +392,20 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
     HIPCHK(launch_fill(h->d_Y, n2, 0.0, st));
     HIPCHK(launch_fill(h->d_Jt, n2, 0.0, st));
     HIPCHK(launch_fill(h->d_Kt, n2, 0.0, st));
-    HIPCHK(launch_fill((double *)h->d_cnt, 32, 0.0, st));
+    HIPCHK(launch_fill((double *)h->d_cnt, kNumCounters, 0.0, st));
+    // class pairs whose quartets had several shifts each in the last finished
+    // build sum the shifts before the transforms
+    if (h->ev_cnt && hipEventQuery(h->ev_cnt) == hipSuccess)
+        for (int k = 0; k < 21; ++k) {
+            const double nq = (double)h->h_cnt[24 + k], nt = (double)h->h_cnt[2 + k];
+            if (nq > 0) h->fold[k] = nt > kFoldRatio * nq;
+        }
 
-    // B3/B4: short-range J and K
+    // B3/B4: short-range J and K.  Per class pair: the density-weighted
+    // screen compacts the neighbour list into FP64 and FP32 work lists, then
+    // one launch per list.
     if (h->parts & PBC_JK_PART_SR) {
+        HIPCHK(launch_fill((double *)h->d_wcnt, 42, 0.0, st));
         SRArgs a{};
         a.pairs = h->d_pairs; a.groups = h->d_groups;
         a.Dt = h->d_Dt; a.Dmax = h->d_Dmax;
@@ -374,18 +418,37 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
         int slot = 0;
         for (int cb = 0; cb < kNumClass; ++cb)
             for (int ck = cb; ck < kNumClass; ++ck, ++slot) {
+                const long e0 = h->nbr_off[slot], e1 = h->nbr_off[slot + 1];
+                if (e1 == e0) continue;
+                // class pairs with a d shell and L >= 4 use one wavefront per group pair (FP64)
+                const bool coop = (kClassL[cb] + kClassL[ck] >= 4) && (cb >= 3 || ck >= 3);
+                // mixed precision: the density screen splits the list into FP64
+                // and FP32 work lists; otherwise the kernels screen in place
+                const bool split = S.fp32_below > 0 && !coop;
+                PartArgs pa{};
+                pa.groups = h->d_groups; pa.gb0 = S.class_start[cb]; pa.gk0 = S.class_start[ck];
+                pa.bra = h->d_nbr_bra + e0; pa.ket = h->d_nbr_ket + e0; pa.n = e1 - e0;
+                pa.Dmax = h->d_Dmax; pa.nshell = S.nshell;
+                pa.d_schwarz = S.d_schwarz; pa.fp32_below = S.fp32_below;
+                pa.split = 1;
+                pa.b64 = h->d_w64b + e0; pa.k64 = h->d_w64k + e0;
+                pa.b32 = h->d_w32b + e0; pa.k32 = h->d_w32k + e0;
+                pa.counts = h->d_wcnt + 2 * slot;
+                if (split) HIPCHK(launch_partition(pa, st));
                 a.slot = slot;
                 a.gb0 = S.class_start[cb];
                 a.gk0 = S.class_start[ck];
                 a.tri = (cb == ck);
-                const long e0 = h->nbr_off[slot], e1 = h->nbr_off[slot + 1];
-                a.nbr_bra = h->d_nbr_bra + e0; a.nbr_ket = h->d_nbr_ket + e0; a.n_entries = e1 - e0;
-                if (a.n_entries == 0) continue;
-                // class pairs with a d shell and L >= 4 use one wavefront per group pair
-                const bool coop = (kClassL[cb] + kClassL[ck] >= 4) && (cb >= 3 || ck >= 3);
-                hipError_t e = coop ? launch_sr_coop(cb, ck, a, st) : launch_sr_jk(cb, ck, a, st);
-                if (e == hipErrorNotSupported) return fail(PBC_JK_ENOTSUP, "d-shell kernels not built");
-                HIPCHK(e);
+                a.max_entries = e1 - e0;
+                for (int prec = 0; prec < (split ? 2 : 1); ++prec) {
+                    a.nbr_bra = !split ? pa.bra : prec ? pa.b32 : pa.b64;
+                    a.nbr_ket = !split ? pa.ket : prec ? pa.k32 : pa.k64;
+                    a.count = !split ? h->d_ncnt + slot : h->d_wcnt + 2 * slot + prec;
+                    hipError_t e = coop ? launch_sr_coop(cb, ck, a, st)
+                                        : launch_sr_jk(cb, ck, a, prec == 1, h->fold[slot], st);
+                    if (e == hipErrorNotSupported) return fail(PBC_JK_ENOTSUP, "d-shell kernels not built");
+                    HIPCHK(e);
+                }
             }
     }
     HIPCHK(hipEventRecord(h->ev[1], st));
@@ -525,6 +588,8 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
         if (E_K) HIPCHK(launch_dot(dD, Ko, m2, h->d_scal + 2, st));
     }
     HIPCHK(hipEventRecord(h->ev[3], st));
+    HIPCHK(hipMemcpyAsync(h->h_cnt, h->d_cnt, kNumCounters * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipEventRecord(h->ev_cnt, st));
     h->timed = true;
     if (E_J || E_K) {
         double e[2];
@@ -742,7 +807,7 @@ int pbc_jk_stats(const pbc_jk *hc, pbc_jk_counters *out)
         HIPCHK(hipEventElapsedTime(&b, h->ev[1], h->ev[2]));
         HIPCHK(hipEventElapsedTime(&c, h->ev[2], h->ev[3]));
         h->st.t_sr_ms = a; h->st.t_lr_ms = b; h->st.t_other_ms = c;
-        unsigned long long cnt[2 + 21 + 1];
+        unsigned long long cnt[kNumCounters];
         HIPCHK(hipMemcpy(cnt, h->d_cnt, sizeof cnt, hipMemcpyDeviceToHost));
         h->st.quartets = (double)cnt[0];
         h->st.terms = (double)cnt[1];

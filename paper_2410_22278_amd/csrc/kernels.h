@@ -11,9 +11,11 @@ struct SRArgs {
     const GroupRec *groups;
     int gb0, gk0;         // first group of the bra and ket classes
     int tri;              // same class: the diagonal group pair has weight 1/2
-    const int *nbr_bra;   // neighbour list of this class pair (bra, ket indices
-    const int *nbr_ket;   //   within their classes), n_entries long
-    long n_entries;
+    const int *nbr_bra;   // work list of this class pair (bra, ket indices within
+    const int *nbr_ket;   //   their classes): the density-screened part of the
+                          //   neighbour list in one precision
+    const unsigned long long *count;   // device: entries in the work list
+    long max_entries;     // host: upper bound of *count (sizes the grid)
     const double *Dt;     // scaled Cartesian density, nbfc x nbfc
     const double *Dmax;   // nshell x nshell block maxima of the Cartesian density
     double *X, *Y;        // J and K halves, nbfc x nbfc
@@ -23,7 +25,8 @@ struct SRArgs {
     double fp32_below;    // > 0: quartets with Q Q w_D below it are evaluated in FP32
     const double *boys;   // kBoysNT x kBoysM
     unsigned long long *counters;   // [0] primitive quartets, [1] (quartet, R1) terms,
-                                    // [2 + slot] terms of this class pair, [23] FP32 terms
+                                    // [2 + slot] terms of this class pair, [23] FP32 terms,
+                                    // [24 + slot] primitive quartets of this class pair
     int slot;             // class-pair index (0..20)
 };
 
@@ -43,7 +46,26 @@ struct NbrArgs {
 };
 hipError_t launch_nbr(const NbrArgs &a, hipStream_t st);
 
-hipError_t launch_sr_jk(int cb, int ck, const SRArgs &a, hipStream_t st);
+// Per-build density screen of one class pair's neighbour list: entries with
+// Qmax_b Qmax_k w_D > d_schwarz are appended (in chunks of 256 that keep
+// their order) to the FP64 list, or to the FP32 list when `split` and the
+// same bound is below fp32_below.  counts[0], counts[1]: list lengths (must
+// be zero on entry).
+struct PartArgs {
+    const GroupRec *groups;
+    int gb0, gk0;
+    const int *bra, *ket;
+    long n;
+    const double *Dmax;
+    int nshell;
+    double d_schwarz, fp32_below;
+    int split;
+    int *b64, *k64, *b32, *k32;
+    unsigned long long *counts;
+};
+hipError_t launch_partition(const PartArgs &a, hipStream_t st);
+
+hipError_t launch_sr_jk(int cb, int ck, const SRArgs &a, bool f32, bool fold, hipStream_t st);
 // class pairs with total angular momentum >= 5 (one wavefront per group pair)
 hipError_t launch_sr_coop(int cb, int ck, const SRArgs &a, hipStream_t st);
 

@@ -75,12 +75,73 @@ __global__ __launch_bounds__(256) void k_nbr(NbrArgs a)
     if (!a.mode && lane == 0) a.counts[bi] = cnt;
 }
 
+// Screen flags of one entry: bit 0 keep in FP64, bit 1 keep in FP32.
+__device__ __forceinline__ int entry_class(const PartArgs &a, long e)
+{
+    const GroupRec &gb = a.groups[a.gb0 + a.bra[e]];
+    const GroupRec &gk = a.groups[a.gk0 + a.ket[e]];
+    const int ns = a.nshell;
+    const int A = gb.shA, B = gb.shB, C = gk.shA, D = gk.shB;
+    double wD = a.Dmax[A * ns + B];
+    wD = fmax(wD, a.Dmax[C * ns + D]);
+    wD = fmax(wD, a.Dmax[A * ns + C]);
+    wD = fmax(wD, a.Dmax[A * ns + D]);
+    wD = fmax(wD, a.Dmax[B * ns + C]);
+    wD = fmax(wD, a.Dmax[B * ns + D]);
+    const double bound = gb.Qmax * gk.Qmax * wD;
+    if (!(bound > a.d_schwarz)) return 0;
+    return (a.split && bound < a.fp32_below) ? 2 : 1;
+}
+
+__global__ __launch_bounds__(256) void k_partition(PartArgs a)
+{
+    __shared__ int s_cnt[2][4];
+    __shared__ unsigned long long s_base[2];
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    for (long c0 = (long)blockIdx.x * 256; c0 < a.n; c0 += (long)gridDim.x * 256) {
+        const long e = c0 + tid;
+        const int f = e < a.n ? entry_class(a, e) : 0;
+        const unsigned long long m64 = __ballot(f == 1), m32 = __ballot(f == 2);
+        const unsigned long long below = (l == 0) ? 0ull : (~0ull >> (64 - l));
+        if (l == 0) {
+            s_cnt[0][w] = __popcll(m64);
+            s_cnt[1][w] = __popcll(m32);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            const int t64 = s_cnt[0][0] + s_cnt[0][1] + s_cnt[0][2] + s_cnt[0][3];
+            const int t32 = s_cnt[1][0] + s_cnt[1][1] + s_cnt[1][2] + s_cnt[1][3];
+            s_base[0] = t64 ? atomicAdd(&a.counts[0], (unsigned long long)t64) : 0ull;
+            s_base[1] = t32 ? atomicAdd(&a.counts[1], (unsigned long long)t32) : 0ull;
+        }
+        __syncthreads();
+        if (f) {
+            const int k = f - 1;
+            const unsigned long long m = k ? m32 : m64;
+            long pos = (long)s_base[k] + __popcll(m & below);
+            for (int u = 0; u < w; ++u) pos += s_cnt[k][u];
+            if (k == 0) { a.b64[pos] = a.bra[e]; a.k64[pos] = a.ket[e]; }
+            else { a.b32[pos] = a.bra[e]; a.k32[pos] = a.ket[e]; }
+        }
+        __syncthreads();   // s_cnt and s_base are rewritten by the next chunk
+    }
+}
+
 }  // namespace
 
 hipError_t launch_nbr(const NbrArgs &a, hipStream_t st)
 {
     if (a.nb <= 0 || a.nk <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_nbr, dim3((a.nb + 3) / 4), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_partition(const PartArgs &a, hipStream_t st)
+{
+    if (a.n <= 0) return hipSuccess;
+    const long chunks = (a.n + 255) / 256;
+    const unsigned grid = (unsigned)(chunks < 8192 ? chunks : 8192);
+    hipLaunchKernelGGL(k_partition, dim3(grid), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

@@ -1,14 +1,17 @@
 // Short-range J and K for the large class pairs (a d shell and total
 // angular momentum L >= 4).
 //
-// One wavefront per group pair: the 64 lanes walk the primitive quartets and
-// lattice shifts of the pair together (every screening decision is uniform
-// across the wave), and split the work of each term:
-//   - R^n_{tuv}, level by level of the recurrence (Sec. 2.3, eq.
-//     R_recursion), values of one level spread over the lanes through LDS;
-//   - the ket transform W[t][cd] = sum_s (-1)^{|s|} E^cd_s R_{t+s};
-//   - the Cartesian block I[ab][cd] = sum_t E^ab_t W[t][cd], each lane owning
-//     a fixed set of (ab, cd) entries accumulated in registers.
+// One wavefront per group pair of the work list; the 64 lanes walk the
+// primitive quartets and lattice shifts of the pair together (every
+// screening decision is uniform across the wave):
+//   - per shift, R^n_{tuv} level by level of the recurrence (Sec. 2.3, eq.
+//     R_recursion), the values of one level spread over the lanes via LDS,
+//     and summed over the shifts of the quartet (FP64, with the quartet's
+//     prefactor) into Rs_{tuv};
+//   - per quartet, the ket transform W[t][cd] += sum_s (-1)^{|s|} E^cd_s
+//     Rs_{t+s}, accumulated over the ket primitives of the bra primitive;
+//   - per bra primitive, the bra transform I[ab][cd] += sum_t E^ab_t W[t][cd],
+//     each lane owning a fixed set of (ab, cd) entries in registers.
 // At the end the block goes through LDS and every J/K target element is
 // summed by one lane and added with one atomic.
 #include <hip/hip_runtime.h>
@@ -41,16 +44,16 @@ __global__ __launch_bounds__(64) void k_sr_coop(SRArgs a)
     constexpr int NAB = NA * NB, NCD = NC * ND;
     constexpr int LAB = LA + LB, LCD = LC + LD;
     constexpr int NH = nherm(L), NHAB = nherm(LAB);
-    constexpr int NBLK = NAB * NCD;
-    constexpr int PER = (NBLK + 63) / 64;
+    constexpr int NBLK = NAB * NCD, NW = NHAB * NCD;
+    constexpr int PER = (NBLK + 63) / 64, PERW = (NW + 63) / 64, PERH = (NH + 63) / 64;
     constexpr int EB = (LA + 1) * (LB + 1) * (LAB + 1), EK = (LC + 1) * (LD + 1) * (LCD + 1);
-
-    constexpr int NWB = (NBLK > NHAB * NCD) ? NBLK : NHAB * NCD;
+    constexpr int NWB = (NBLK > NW) ? NBLK : NW;
     // the Boys lookups of a term are uniform over the wave: the table is read
     // from global memory (one broadcast load per coefficient)
     const double *tab = a.boys + L;
     __shared__ double sR[2][NH];
-    __shared__ double sW[NWB];        // ket transform; then the final block
+    __shared__ double sRs[NH];
+    __shared__ double sW[NWB];        // W of one bra primitive; then the final block
     __shared__ double sEb[3][EB], sEk[3][EK];
     __shared__ int sT[NH][3];   // (t,u,v) of each Hermite index
     double *sBlk = sW;
@@ -61,8 +64,10 @@ __global__ __launch_bounds__(64) void k_sr_coop(SRArgs a)
             for (int v = 0; v <= L - t - u; ++v)
                 if (lane == 0) { int h = hidx(t, u, v); sT[h][0] = t; sT[h][1] = u; sT[h][2] = v; }
     __syncthreads();
+    const long count = (long)*a.count;
+    unsigned long long cnt_q = 0, cnt_t = 0;
 
-    const long e = blockIdx.x;
+    for (long e = blockIdx.x; e < count; e += gridDim.x) {
     const int bi = a.nbr_bra[e], j = a.nbr_ket[e];
     const GroupRec gb = a.groups[a.gb0 + bi];
     const GroupRec gk = a.groups[a.gk0 + j];
@@ -74,12 +79,13 @@ __global__ __launch_bounds__(64) void k_sr_coop(SRArgs a)
     wD = fmax(wD, a.Dmax[A * ns + D]);
     wD = fmax(wD, a.Dmax[B * ns + C]);
     wD = fmax(wD, a.Dmax[B * ns + D]);
-    if (!(gb.Qmax * gk.Qmax * wD > a.d_schwarz)) return;   // uniform over the block
+    // group-level density screen (already applied when the list was compacted)
+    if (!(gb.Qmax * gk.Qmax * wD > a.d_schwarz)) continue;   // uniform over the wave
 
     double acc[PER];
 #pragma unroll
     for (int i = 0; i < PER; ++i) acc[i] = 0.0;
-    unsigned long long cnt_q = 0, cnt_t = 0;
+    long ent_terms = 0;
 
     for (int pb = gb.pstart; pb < gb.pend; ++pb) {
         const PairRec Pb = a.pairs[pb];
@@ -90,6 +96,10 @@ __global__ __launch_bounds__(64) void k_sr_coop(SRArgs a)
                 for (int jj = 0; jj <= LB; ++jj)
                     for (int t = 0; t <= LAB; ++t) sEb[lane][(i * (LB + 1) + jj) * (LAB + 1) + t] = E.v[i][jj][t];
         }
+        double Wacc[PERW];
+#pragma unroll
+        for (int i = 0; i < PERW; ++i) Wacc[i] = 0.0;
+        bool any_k = false;
         for (int pk = gk.pstart; pk < gk.pend; ++pk) {
             const PairRec Pk = a.pairs[pk];
             if (!(Pb.Q * Pk.Q * wD > a.d_schwarz)) continue;
@@ -98,19 +108,13 @@ __global__ __launch_bounds__(64) void k_sr_coop(SRArgs a)
             if (!quartet_sphere(Pb, Pk, a.w2, a.d_ewald_R, rad2)) continue;
             const double p = Pb.p, q = Pk.p, pq = p * q;
             const double rho = pq / (p + q);
-            const double pref = Pb.cpre * Pk.cpre * kTwoPi52 / (pq * sqrt(p + q));
-            __syncthreads();   // previous users of sEk are done
-            if (lane < 3) {
-                EAxis<LC, LD> E;
-                herm_axis<LC, LD>(0.5 / q, Pk.PA[lane], Pk.PB[lane], E);
-                for (int i = 0; i <= LC; ++i)
-                    for (int jj = 0; jj <= LD; ++jj)
-                        for (int t = 0; t <= LCD; ++t) sEk[lane][(i * (LD + 1) + jj) * (LCD + 1) + t] = E.v[i][jj][t];
-            }
-            __syncthreads();
+            double Rs[PERH];
+#pragma unroll
+            for (int i = 0; i < PERH; ++i) Rs[i] = 0.0;
+            int nimg = 0;
             const double cen[3] = {Pb.P[0] - Pk.P[0], Pb.P[1] - Pk.P[1], Pb.P[2] - Pk.P[2]};
             for_images(a.lat, cen, rad2, a.rcap2, [&](const double *Lv, double L2) {
-                ++cnt_t;
+                ++nimg;
                 double R0[L + 1];
                 sr_R0<L, kBoysM>(rho, a.w2, L2, tab, R0);
                 // R recurrence, one level at a time: level n holds t+u+v <= L-n
@@ -131,8 +135,36 @@ __global__ __launch_bounds__(64) void k_sr_coop(SRArgs a)
                     cur = nxt;
                     __syncthreads();
                 }
-                // ket transform W[t][cd], t+u+v <= LAB
-                for (int w = lane; w < NHAB * NCD; w += 64) {
+#pragma unroll
+                for (int i = 0; i < PERH; ++i) {
+                    const int h = lane + 64 * i;
+                    if (h < NH) Rs[i] += sR[cur][h];
+                }
+                __syncthreads();   // sR is rewritten by the next shift
+            });
+            if (nimg == 0) continue;
+            cnt_t += nimg;
+            ent_terms += nimg;
+            any_k = true;
+            const double pref = Pb.cpre * Pk.cpre * kTwoPi52 / (pq * sqrt(p + q));
+#pragma unroll
+            for (int i = 0; i < PERH; ++i) {
+                const int h = lane + 64 * i;
+                if (h < NH) sRs[h] = pref * Rs[i];
+            }
+            if (lane < 3) {
+                EAxis<LC, LD> E;
+                herm_axis<LC, LD>(0.5 / q, Pk.PA[lane], Pk.PB[lane], E);
+                for (int i = 0; i <= LC; ++i)
+                    for (int jj = 0; jj <= LD; ++jj)
+                        for (int t = 0; t <= LCD; ++t) sEk[lane][(i * (LD + 1) + jj) * (LCD + 1) + t] = E.v[i][jj][t];
+            }
+            __syncthreads();
+            // ket transform into the lane's W[t][cd] entries, t+u+v <= LAB
+#pragma unroll
+            for (int i = 0; i < PERW; ++i) {
+                const int w = lane + 64 * i;
+                if (w < NW) {
                     const int th = w / NCD, cd = w - th * NCD;
                     const int ic = cd / ND, id = cd - ic * ND;
                     const int t = sT[th][0], u = sT[th][1], v = sT[th][2];
@@ -145,40 +177,48 @@ __global__ __launch_bounds__(64) void k_sr_coop(SRArgs a)
                             const double ey = ex * sEk[1][(ccy * (LD + 1) + dcy) * (LCD + 1) + uu];
                             for (int vv = 0; vv <= ccz + dcz; ++vv) {
                                 const double ez = ey * sEk[2][(ccz * (LD + 1) + dcz) * (LCD + 1) + vv];
-                                const double rv = sR[cur][hidx(t + tt, u + uu, v + vv)];
+                                const double rv = sRs[hidx(t + tt, u + uu, v + vv)];
                                 s += ((tt + uu + vv) & 1) ? -ez * rv : ez * rv;
                             }
                         }
                     }
-                    sW[w] = s;
+                    Wacc[i] += s;
                 }
-                __syncthreads();
-                // bra transform into the lane's block entries
-#pragma unroll
-                for (int i = 0; i < PER; ++i) {
-                    const int k = lane + 64 * i;
-                    if (k < NBLK) {
-                        const int ab = k / NCD, cd = k - ab * NCD;
-                        const int ia = ab / NB, ib = ab - ia * NB;
-                        const int acx = cx(LA, ia), acy = cy(LA, ia), acz = cz(LA, ia);
-                        const int bcx = cx(LB, ib), bcy = cy(LB, ib), bcz = cz(LB, ib);
-                        double s = 0.0;
-                        for (int t = 0; t <= acx + bcx; ++t) {
-                            const double ex = sEb[0][(acx * (LB + 1) + bcx) * (LAB + 1) + t];
-                            for (int u = 0; u <= acy + bcy; ++u) {
-                                const double ey = ex * sEb[1][(acy * (LB + 1) + bcy) * (LAB + 1) + u];
-                                for (int v = 0; v <= acz + bcz; ++v)
-                                    s += ey * sEb[2][(acz * (LB + 1) + bcz) * (LAB + 1) + v] * sW[hidx(t, u, v) * NCD + cd];
-                            }
-                        }
-                        acc[i] += pref * s;
-                    }
-                }
-                __syncthreads();   // sW and sR are reused by the next term
-            });
+            }
+            __syncthreads();   // sRs and sEk are rewritten by the next ket primitive
         }
-        __syncthreads();   // sEb is rewritten by the next bra primitive
+        if (any_k) {
+#pragma unroll
+            for (int i = 0; i < PERW; ++i) {
+                const int w = lane + 64 * i;
+                if (w < NW) sW[w] = Wacc[i];
+            }
+            __syncthreads();
+            // bra transform into the lane's block entries
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                const int k = lane + 64 * i;
+                if (k < NBLK) {
+                    const int ab = k / NCD, cd = k - ab * NCD;
+                    const int ia = ab / NB, ib = ab - ia * NB;
+                    const int acx = cx(LA, ia), acy = cy(LA, ia), acz = cz(LA, ia);
+                    const int bcx = cx(LB, ib), bcy = cy(LB, ib), bcz = cz(LB, ib);
+                    double s = 0.0;
+                    for (int t = 0; t <= acx + bcx; ++t) {
+                        const double ex = sEb[0][(acx * (LB + 1) + bcx) * (LAB + 1) + t];
+                        for (int u = 0; u <= acy + bcy; ++u) {
+                            const double ey = ex * sEb[1][(acy * (LB + 1) + bcy) * (LAB + 1) + u];
+                            for (int v = 0; v <= acz + bcz; ++v)
+                                s += ey * sEb[2][(acz * (LB + 1) + bcz) * (LAB + 1) + v] * sW[hidx(t, u, v) * NCD + cd];
+                        }
+                    }
+                    acc[i] += s;
+                }
+            }
+        }
+        __syncthreads();   // sEb and sW are rewritten by the next bra primitive
     }
+    if (ent_terms == 0) continue;   // uniform over the wave
 
     // contraction with the density through LDS
 #pragma unroll
@@ -230,6 +270,8 @@ __global__ __launch_bounds__(64) void k_sr_coop(SRArgs a)
             atomicAdd(&a.Y[(long)(aoB + ib) * n + aoD + id], w * s);
         }
     }
+    __syncthreads();   // sBlk is rewritten by the next entry
+    }
     if (lane == 0) {
         atomicAdd(&a.counters[0], cnt_q);
         atomicAdd(&a.counters[1], cnt_t);
@@ -240,8 +282,9 @@ __global__ __launch_bounds__(64) void k_sr_coop(SRArgs a)
 template <int LA, int LB, int LC, int LD>
 hipError_t launch_coop(const SRArgs &a, hipStream_t st)
 {
-    if (a.n_entries <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_sr_coop<LA, LB, LC, LD>), dim3((unsigned)a.n_entries), dim3(64), 0, st, a);
+    if (a.max_entries <= 0) return hipSuccess;
+    const long grid = a.max_entries < 65536 ? a.max_entries : 65536;
+    hipLaunchKernelGGL((k_sr_coop<LA, LB, LC, LD>), dim3((unsigned)grid), dim3(64), 0, st, a);
     return hipGetLastError();
 }
 

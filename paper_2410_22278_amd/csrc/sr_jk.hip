@@ -11,12 +11,21 @@
 // with w = 1/2 on the diagonal group pair and 1 otherwise (the primitive
 // symmetry weights are folded into the pair prefactors).
 //
-// Mapping: one lane per entry of the class pair's neighbour list (group
-// pairs that have at least one real-space term; entries of one bra group
-// are consecutive, so a wavefront mostly shares its bra data).  Each lane
-// applies the density-weighted screen, the real-space sphere and the image
-// search of every primitive quartet of its group pair.
+// Mapping: one lane per entry of the class pair's work list (the group pairs
+// of the neighbour list that pass this build's density-weighted screen, in
+// one precision; entries of one bra group are consecutive, so a wavefront
+// mostly shares its bra data).  Each lane screens the primitive quartets of
+// its group pair and finds the lattice shifts R1 inside each quartet's
+// real-space sphere.  With FOLD the Hermite integrals R_{tuv} of the shifts
+// are summed in FP64 before the Hermite -> Cartesian transforms, which then
+// run once per quartet (the better order when quartets have several shifts,
+// as in small cells); without it the transforms run per shift.
+// In the FP32 variant R_{tuv} of each shift and the transforms are FP32
+// (the Boys values stay FP64 for small arguments); the lattice sum and the
+// block accumulation are FP64.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "device_math.h"
 #include "kernels.h"
@@ -80,12 +89,89 @@ __device__ __forceinline__ void add_term(const EAxis<LA, LB> &Ex, const EAxis<LA
         }
 }
 
-template <int LA, int LB, int LC, int LD, bool MIX>
+// Adds the density contractions of one contracted block into the J and K
+// halves (hardware FP64 atomics).
+template <int LA, int LB, int LC, int LD>
+__device__ __forceinline__ void scatter_block(const SRArgs &a, const double (&acc)[ncart(LA)][ncart(LB)][ncart(LC)][ncart(LD)],
+                                              double w, int aoA, int aoB, int aoC, int aoD)
+{
+    constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
+    const double *Dt = a.Dt;
+    const int n = a.nbfc;
+#pragma unroll
+    for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+        for (int ib = 0; ib < NB; ++ib) {
+            double s = 0.0;
+#pragma unroll
+            for (int ic = 0; ic < NC; ++ic)
+#pragma unroll
+                for (int id = 0; id < ND; ++id) s += acc[ia][ib][ic][id] * Dt[(aoC + ic) * n + aoD + id];
+            atomicAdd(&a.X[(aoA + ia) * n + aoB + ib], 2.0 * w * s);
+        }
+#pragma unroll
+    for (int ic = 0; ic < NC; ++ic)
+#pragma unroll
+        for (int id = 0; id < ND; ++id) {
+            double s = 0.0;
+#pragma unroll
+            for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+                for (int ib = 0; ib < NB; ++ib) s += acc[ia][ib][ic][id] * Dt[(aoA + ia) * n + aoB + ib];
+            atomicAdd(&a.X[(aoC + ic) * n + aoD + id], 2.0 * w * s);
+        }
+#pragma unroll
+    for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+        for (int ic = 0; ic < NC; ++ic) {
+            double s = 0.0;
+#pragma unroll
+            for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+                for (int id = 0; id < ND; ++id) s += acc[ia][ib][ic][id] * Dt[(aoB + ib) * n + aoD + id];
+            atomicAdd(&a.Y[(aoA + ia) * n + aoC + ic], w * s);
+        }
+#pragma unroll
+    for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+        for (int ic = 0; ic < NC; ++ic) {
+            double s = 0.0;
+#pragma unroll
+            for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+                for (int id = 0; id < ND; ++id) s += acc[ia][ib][ic][id] * Dt[(aoA + ia) * n + aoD + id];
+            atomicAdd(&a.Y[(aoB + ib) * n + aoC + ic], w * s);
+        }
+#pragma unroll
+    for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+        for (int id = 0; id < ND; ++id) {
+            double s = 0.0;
+#pragma unroll
+            for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+                for (int ic = 0; ic < NC; ++ic) s += acc[ia][ib][ic][id] * Dt[(aoB + ib) * n + aoC + ic];
+            atomicAdd(&a.Y[(aoA + ia) * n + aoD + id], w * s);
+        }
+#pragma unroll
+    for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+        for (int id = 0; id < ND; ++id) {
+            double s = 0.0;
+#pragma unroll
+            for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+                for (int ic = 0; ic < NC; ++ic) s += acc[ia][ib][ic][id] * Dt[(aoA + ia) * n + aoC + ic];
+            atomicAdd(&a.Y[(aoB + ib) * n + aoD + id], w * s);
+        }
+}
+
+template <int LA, int LB, int LC, int LD, typename V, bool FOLD>
 __global__ __launch_bounds__(256) void k_sr_jk(SRArgs a)
 {
     constexpr int L = LA + LB + LC + LD;
     constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
-    constexpr int LAB = LA + LB;
+    constexpr bool F32 = sizeof(V) == 4;
     __shared__ double tab[kBoysNT * kBoysTerms];
     for (int i = threadIdx.x; i < kBoysNT * kBoysTerms; i += blockDim.x) {
         int k = i / kBoysTerms, j = i - k * kBoysTerms;
@@ -93,11 +179,11 @@ __global__ __launch_bounds__(256) void k_sr_jk(SRArgs a)
     }
     __syncthreads();
     const int lane = threadIdx.x & 63;
-    const int n = a.nbfc, ns = a.nshell;
-    unsigned long long cnt_q = 0, cnt_t = 0, cnt_f = 0;
+    const int ns = a.nshell;
+    unsigned long long cnt_q = 0, cnt_t = 0;
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
 
-    if (e < a.n_entries) {
+    if (e < (long)*a.count) {
         const int bi = a.nbr_bra[e], j = a.nbr_ket[e];
         const GroupRec gb = a.groups[a.gb0 + bi];
         const GroupRec gk = a.groups[a.gk0 + j];
@@ -108,7 +194,6 @@ __global__ __launch_bounds__(256) void k_sr_jk(SRArgs a)
         wD = fmax(wD, a.Dmax[A * ns + D]);
         wD = fmax(wD, a.Dmax[B * ns + C]);
         wD = fmax(wD, a.Dmax[B * ns + D]);
-        if (gb.Qmax * gk.Qmax * wD > a.d_schwarz) {
         double acc[NA][NB][NC][ND];
 #pragma unroll
         for (int i0 = 0; i0 < NA; ++i0)
@@ -118,8 +203,11 @@ __global__ __launch_bounds__(256) void k_sr_jk(SRArgs a)
                 for (int i2 = 0; i2 < NC; ++i2)
 #pragma unroll
                     for (int i3 = 0; i3 < ND; ++i3) acc[i0][i1][i2][i3] = 0.0;
+        unsigned long long ent_terms = 0;
+        // group-level density screen (already applied when the list was compacted)
+        const int pb_end = (gb.Qmax * gk.Qmax * wD > a.d_schwarz) ? gb.pend : gb.pstart;
 
-        for (int pb = gb.pstart; pb < gb.pend; ++pb) {
+        for (int pb = gb.pstart; pb < pb_end; ++pb) {
             const PairRec Pb = a.pairs[pb];
             EAxis<LA, LB> Ex, Ey, Ez;
             const double hb = 0.5 / Pb.p;
@@ -141,122 +229,109 @@ __global__ __launch_bounds__(256) void k_sr_jk(SRArgs a)
                 herm_axis<LC, LD>(hk, Pk.PA[1], Pk.PB[1], Fy);
                 herm_axis<LC, LD>(hk, Pk.PA[2], Pk.PB[2], Fz);
                 const double cen[3] = {Pb.P[0] - Pk.P[0], Pb.P[1] - Pk.P[1], Pb.P[2] - Pk.P[2]};
-                const bool lowp = MIX && (Pb.Q * Pk.Q * wD < a.fp32_below);
-                for_images(a.lat, cen, rad2, a.rcap2, [&](const double *Lv, double L2) {
-                    ++cnt_t;
-                    if (MIX && lowp) {
-                        ++cnt_f;
-                        float R0[L + 1];
-                        sr_R0_mixed<L>(rho, a.w2, L2, tab, R0);
-                        float R[L + 1][L + 1][L + 1];
-                        herm_R<L, float>(R0, (float)Lv[0], (float)Lv[1], (float)Lv[2], R);
-                        add_term<LA, LB, LC, LD, float>(Ex, Ey, Ez, Fx, Fy, Fz, R, pref, acc);
-                    } else {
-                        double R0[L + 1];
-                        sr_R0<L>(rho, a.w2, L2, tab, R0);
-                        double R[L + 1][L + 1][L + 1];
-                        herm_R<L, double>(R0, Lv[0], Lv[1], Lv[2], R);
-                        add_term<LA, LB, LC, LD, double>(Ex, Ey, Ez, Fx, Fy, Fz, R, pref, acc);
-                    }
-                });
+                if (FOLD) {
+                    // lattice sum of the Hermite integrals in FP64, one transform
+                    double Rs[L + 1][L + 1][L + 1];
+#pragma unroll
+                    for (int t = 0; t <= L; ++t)
+#pragma unroll
+                        for (int u = 0; u <= L - t; ++u)
+#pragma unroll
+                            for (int v = 0; v <= L - t - u; ++v) Rs[t][u][v] = 0.0;
+                    int nimg = 0;
+                    for_images(a.lat, cen, rad2, a.rcap2, [&](const double *Lv, double L2) {
+                        ++nimg;
+                        if (F32) {
+                            float R0[L + 1];
+                            sr_R0_mixed<L>(rho, a.w2, L2, tab, R0);
+                            float R[L + 1][L + 1][L + 1];
+                            herm_R<L, float>(R0, (float)Lv[0], (float)Lv[1], (float)Lv[2], R);
+#pragma unroll
+                            for (int t = 0; t <= L; ++t)
+#pragma unroll
+                                for (int u = 0; u <= L - t; ++u)
+#pragma unroll
+                                    for (int v = 0; v <= L - t - u; ++v) Rs[t][u][v] += (double)R[t][u][v];
+                        } else {
+                            double R0[L + 1];
+                            sr_R0<L>(rho, a.w2, L2, tab, R0);
+                            double R[L + 1][L + 1][L + 1];
+                            herm_R<L, double>(R0, Lv[0], Lv[1], Lv[2], R);
+#pragma unroll
+                            for (int t = 0; t <= L; ++t)
+#pragma unroll
+                                for (int u = 0; u <= L - t; ++u)
+#pragma unroll
+                                    for (int v = 0; v <= L - t - u; ++v) Rs[t][u][v] += R[t][u][v];
+                        }
+                    });
+                    if (nimg == 0) continue;
+                    cnt_t += nimg;
+                    ent_terms += nimg;
+                    V Rv[L + 1][L + 1][L + 1];
+#pragma unroll
+                    for (int t = 0; t <= L; ++t)
+#pragma unroll
+                        for (int u = 0; u <= L - t; ++u)
+#pragma unroll
+                            for (int v = 0; v <= L - t - u; ++v) Rv[t][u][v] = (V)Rs[t][u][v];
+                    add_term<LA, LB, LC, LD, V>(Ex, Ey, Ez, Fx, Fy, Fz, Rv, pref, acc);
+                } else {
+                    for_images(a.lat, cen, rad2, a.rcap2, [&](const double *Lv, double L2) {
+                        ++cnt_t;
+                        ++ent_terms;
+                        if (F32) {
+                            float R0[L + 1];
+                            sr_R0_mixed<L>(rho, a.w2, L2, tab, R0);
+                            float R[L + 1][L + 1][L + 1];
+                            herm_R<L, float>(R0, (float)Lv[0], (float)Lv[1], (float)Lv[2], R);
+                            add_term<LA, LB, LC, LD, float>(Ex, Ey, Ez, Fx, Fy, Fz, R, pref, acc);
+                        } else {
+                            double R0[L + 1];
+                            sr_R0<L>(rho, a.w2, L2, tab, R0);
+                            double R[L + 1][L + 1][L + 1];
+                            herm_R<L, double>(R0, Lv[0], Lv[1], Lv[2], R);
+                            add_term<LA, LB, LC, LD, double>(Ex, Ey, Ez, Fx, Fy, Fz, R, pref, acc);
+                        }
+                    });
+                }
             }
         }
-
-        // contraction with the density and accumulation of the J, K halves
-        const double w = (a.tri && j == bi) ? 0.5 : 1.0;
-        const double *Dt = a.Dt;
-        const int aoA = gb.aoA, aoB = gb.aoB, aoC = gk.aoA, aoD = gk.aoB;
-#pragma unroll
-        for (int ia = 0; ia < NA; ++ia)
-#pragma unroll
-            for (int ib = 0; ib < NB; ++ib) {
-                double s = 0.0;
-#pragma unroll
-                for (int ic = 0; ic < NC; ++ic)
-#pragma unroll
-                    for (int id = 0; id < ND; ++id) s += acc[ia][ib][ic][id] * Dt[(aoC + ic) * n + aoD + id];
-                atomicAdd(&a.X[(aoA + ia) * n + aoB + ib], 2.0 * w * s);
-            }
-#pragma unroll
-        for (int ic = 0; ic < NC; ++ic)
-#pragma unroll
-            for (int id = 0; id < ND; ++id) {
-                double s = 0.0;
-#pragma unroll
-                for (int ia = 0; ia < NA; ++ia)
-#pragma unroll
-                    for (int ib = 0; ib < NB; ++ib) s += acc[ia][ib][ic][id] * Dt[(aoA + ia) * n + aoB + ib];
-                atomicAdd(&a.X[(aoC + ic) * n + aoD + id], 2.0 * w * s);
-            }
-#pragma unroll
-        for (int ia = 0; ia < NA; ++ia)
-#pragma unroll
-            for (int ic = 0; ic < NC; ++ic) {
-                double s = 0.0;
-#pragma unroll
-                for (int ib = 0; ib < NB; ++ib)
-#pragma unroll
-                    for (int id = 0; id < ND; ++id) s += acc[ia][ib][ic][id] * Dt[(aoB + ib) * n + aoD + id];
-                atomicAdd(&a.Y[(aoA + ia) * n + aoC + ic], w * s);
-            }
-#pragma unroll
-        for (int ib = 0; ib < NB; ++ib)
-#pragma unroll
-            for (int ic = 0; ic < NC; ++ic) {
-                double s = 0.0;
-#pragma unroll
-                for (int ia = 0; ia < NA; ++ia)
-#pragma unroll
-                    for (int id = 0; id < ND; ++id) s += acc[ia][ib][ic][id] * Dt[(aoA + ia) * n + aoD + id];
-                atomicAdd(&a.Y[(aoB + ib) * n + aoC + ic], w * s);
-            }
-#pragma unroll
-        for (int ia = 0; ia < NA; ++ia)
-#pragma unroll
-            for (int id = 0; id < ND; ++id) {
-                double s = 0.0;
-#pragma unroll
-                for (int ib = 0; ib < NB; ++ib)
-#pragma unroll
-                    for (int ic = 0; ic < NC; ++ic) s += acc[ia][ib][ic][id] * Dt[(aoB + ib) * n + aoC + ic];
-                atomicAdd(&a.Y[(aoA + ia) * n + aoD + id], w * s);
-            }
-#pragma unroll
-        for (int ib = 0; ib < NB; ++ib)
-#pragma unroll
-            for (int id = 0; id < ND; ++id) {
-                double s = 0.0;
-#pragma unroll
-                for (int ia = 0; ia < NA; ++ia)
-#pragma unroll
-                    for (int ic = 0; ic < NC; ++ic) s += acc[ia][ib][ic][id] * Dt[(aoA + ia) * n + aoC + ic];
-                atomicAdd(&a.Y[(aoB + ib) * n + aoD + id], w * s);
-            }
+        if (ent_terms > 0) {
+            const double w = (a.tri && j == bi) ? 0.5 : 1.0;
+            scatter_block<LA, LB, LC, LD>(a, acc, w, gb.aoA, gb.aoB, gk.aoA, gk.aoB);
         }
     }
     // per-lane counters, summed across the wave before one atomic each
     for (int off = 32; off > 0; off >>= 1) {
         cnt_q += __shfl_down(cnt_q, off, 64);
         cnt_t += __shfl_down(cnt_t, off, 64);
-        cnt_f += __shfl_down(cnt_f, off, 64);
     }
     if (lane == 0) {
         atomicAdd(&a.counters[0], cnt_q);
         atomicAdd(&a.counters[1], cnt_t);
         atomicAdd(&a.counters[2 + a.slot], cnt_t);
-        if (MIX) atomicAdd(&a.counters[23], cnt_f);
+        atomicAdd(&a.counters[24 + a.slot], cnt_q);
+        if (F32) atomicAdd(&a.counters[23], cnt_t);
     }
 }
 
-template <int LA, int LB, int LC, int LD>
-hipError_t launch_one(const SRArgs &a, hipStream_t st)
+// Grid: enough blocks of 256 lanes for the work list's upper bound, capped;
+// the kernel strides over the actual device-side count.
+inline dim3 sr_grid(long max_entries)
 {
-    if (a.n_entries <= 0) return hipSuccess;
-    dim3 grid((unsigned)((a.n_entries + 255) / 256)), block(256);
-    if (a.fp32_below > 0)
-        hipLaunchKernelGGL((k_sr_jk<LA, LB, LC, LD, true>), grid, block, 0, st, a);
-    else
-        hipLaunchKernelGGL((k_sr_jk<LA, LB, LC, LD, false>), grid, block, 0, st, a);
+    return dim3((unsigned)std::max(1L, (max_entries + 255) / 256));
+}
+
+template <int LA, int LB, int LC, int LD>
+hipError_t launch_one(const SRArgs &a, bool f32, bool fold, hipStream_t st)
+{
+    if (a.max_entries <= 0) return hipSuccess;
+    const dim3 g = sr_grid(a.max_entries), b(256);
+    if (f32 && fold) hipLaunchKernelGGL((k_sr_jk<LA, LB, LC, LD, float, true>), g, b, 0, st, a);
+    else if (f32) hipLaunchKernelGGL((k_sr_jk<LA, LB, LC, LD, float, false>), g, b, 0, st, a);
+    else if (fold) hipLaunchKernelGGL((k_sr_jk<LA, LB, LC, LD, double, true>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((k_sr_jk<LA, LB, LC, LD, double, false>), g, b, 0, st, a);
     return hipGetLastError();
 }
 
@@ -264,18 +339,20 @@ constexpr int kLa[kNumClass] = {0, 1, 1, 2, 2, 2};
 constexpr int kLb[kNumClass] = {0, 0, 1, 0, 1, 2};
 
 template <int CB, int CK>
-hipError_t launch_pair(const SRArgs &a, hipStream_t st)
+hipError_t launch_pair(const SRArgs &a, bool f32, bool fold, hipStream_t st)
 {
-    return launch_one<kLa[CB], kLb[CB], kLa[CK], kLb[CK]>(a, st);
+    return launch_one<kLa[CB], kLb[CB], kLa[CK], kLb[CK]>(a, f32, fold, st);
 }
 
 }  // namespace
 
-// Launches the kernel of bra class cb and ket class ck (cb <= ck).
-hipError_t launch_sr_jk(int cb, int ck, const SRArgs &a, hipStream_t st)
+// Launches the kernel of bra class cb and ket class ck (cb <= ck) on one
+// work list, in FP32 (f32) or FP64, with or without the lattice sum folded
+// into the Hermite integrals.
+hipError_t launch_sr_jk(int cb, int ck, const SRArgs &a, bool f32, bool fold, hipStream_t st)
 {
 #define PBCJK_CASE(X, Y) \
-    if (cb == X && ck == Y) return launch_pair<X, Y>(a, st);
+    if (cb == X && ck == Y) return launch_pair<X, Y>(a, f32, fold, st);
     PBCJK_CASE(0, 0) PBCJK_CASE(0, 1) PBCJK_CASE(0, 2) PBCJK_CASE(1, 1) PBCJK_CASE(1, 2) PBCJK_CASE(2, 2)
 #if PBCJK_WITH_D
     // d-shell class pairs up to total angular momentum 3; larger ones run in
