@@ -23,6 +23,35 @@ FP64_MFMA_PEAK_TFLOPS = 78.6
 FP64_VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 CLASSES = [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2)]
+CLASS_NAMES = ["ss", "ps", "pp", "ds", "dp", "dd"]
+SLOTS = [(cb, ck) for cb in range(6) for ck in range(cb, 6)]
+CSRC = os.path.join(ROOT, "paper_2410_22278_amd", "csrc")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def _sha256(path):
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def traffic_for(name):
+    """HBM bytes per launch of `name` from the committed counter summary, or
+    None when there is none or the kernel's source changed since."""
+    import json as _json
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = _json.load(f)
+    except (OSError, ValueError):
+        return None
+    for r in rec.get("kernels", []):
+        if r.get("name") != name:
+            continue
+        srcs = r.get("sources", {})
+        if srcs and all(os.path.exists(os.path.join(CSRC, k)) and _sha256(os.path.join(CSRC, k)) == v
+                        for k, v in srcs.items()):
+            return r.get("bytes_per_launch")
+    return None
 
 
 def _nh(l):
@@ -47,14 +76,6 @@ def sr_flops_per_term(cb, ck):
             + 2 * _nh(la + lb) * nab * ncd)
 
 
-def sr_flops(terms_class):
-    tot, slot = 0.0, 0
-    for cb in range(6):
-        for ck in range(cb, 6):
-            tot += terms_class[slot] * sr_flops_per_term(cb, ck)
-            slot += 1
-    return tot
-
 WORKLOADS = {
     "cfg1": "cubic a=5.0 A, 8 atoms, 2s+1p per atom (3 prims, exps 0.1-20), nbf 40, "
             "omega 0.3, delta 1e-10, image cap 10 A, |G| <= 3, D = C C^T (40x8), FP64",
@@ -62,6 +83,9 @@ WORKLOADS = {
             "nbf 832, omega 0.3, delta 1e-10, D = C C^T (832x320), FP64",
     "cfg3": "the 64-water cell of cfg2 in mixed precision: FP32 short-range quartets below a "
             "density-weighted bound of 1e-6, FP64 accumulation and reciprocal sum",
+    "cfg5": "serving stream: cubic H/C/O cells of 8-216 atoms (log-uniform) at 0.1 atoms/A^3, mixed precision, "
+            "D = C C^T with nbf/4 orbitals, Poisson arrivals at 0.8x the measured saturated rate, through the "
+            "library's request server (4 slots, HBM arena admission)",
 }
 
 
@@ -101,6 +125,60 @@ def cpu_baseline(system, name):
                        f"by {len(G)}/{ng_s}; self term in full; est. full build {total:.0f} s")}
 
 
+def serve(args, np, torch, inputs, pbcjk):
+    """cfg5: a stream of requests through the library's request server."""
+    import threading
+    reqs = [inputs.serving_request(i) for i in range(args.requests)]
+    print(f"cfg5: {len(reqs)} requests, natom {min(r.natom for r in reqs)}-{max(r.natom for r in reqs)}, "
+          f"nbf {min(r.nbf for r in reqs)}-{max(r.nbf for r in reqs)}", file=sys.stderr, flush=True)
+
+    def run(arrivals):
+        with pbcjk.Server(slots=4, cache_cells=False) as srv:
+            t0 = time.perf_counter()
+            tickets = [None] * len(reqs)
+
+            def feeder():
+                for i, r in enumerate(reqs):
+                    dt = t0 + arrivals[i] - time.perf_counter()
+                    if dt > 0:
+                        time.sleep(dt)
+                    tickets[i] = srv.submit(r)
+            th = threading.Thread(target=feeder)
+            th.start()
+            th.join()
+            res = [srv.wait(t) for t in tickets]
+            wall = time.perf_counter() - t0
+            st = srv.stats()
+        bad = [r["error"] for r in res if r["status"] != 0]
+        if bad:
+            raise RuntimeError(f"cfg5: {len(bad)} requests failed: {bad[:3]}")
+        return res, wall, st
+
+    # saturated: every request queued at t = 0
+    res_sat, wall_sat, _ = run(np.zeros(len(reqs)))
+    sat = len(reqs) / wall_sat
+    print(f"saturated: {sat:.3f} builds/s ({wall_sat:.1f} s)", file=sys.stderr, flush=True)
+    rate = args.rate_factor * sat
+    arr = inputs.serving_arrivals(len(reqs), rate=rate)
+    res, wall, st = run(arr - arr[0])
+    lat = np.array([r["latency_ms"] for r in res])
+    build = np.array([r["build_ms"] for r in res])
+    out = {
+        "metric": METRIC, "value": len(reqs) / wall, "unit": "builds/s", "n_gpus": 1,
+        "steps": len(reqs), "warmup": 0, "ms_per_step": 1000.0 * wall / len(reqs), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": f"cfg5: {WORKLOADS['cfg5']}", "requests": len(reqs),
+                   "arrival_rate_per_s": rate, "saturated_builds_per_s": sat,
+                   "precision": "mixed (fp32 below 1e-06)"},
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "build_ms_p50": float(np.percentile(build, 50)), "build_ms_max": float(build.max()),
+        "server": {k: st[k] for k in ("peak_running", "peak_in_use", "budget", "retries")},
+        "roofline": None, "cpu_baseline": None,
+        "note": "roofline and cpu_baseline are reported on the single-cell workloads (cfg1-cfg3)",
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +186,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--requests", type=int, default=32, help="cfg5: requests of the stream to run")
+    ap.add_argument("--rate-factor", type=float, default=0.8, help="cfg5: arrival rate / saturated rate")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-sized float64 buffer 3 times on the GPU (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs the hot path on one GPU only; --gpus above 1 is not "
@@ -121,6 +203,19 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        n = args.copy_probe * 1048576 // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": 3}))
+        return
+    if args.workload == "cfg5":
+        serve(args, np, torch, inputs, pbcjk)
+        return
     system = inputs.CONFIGS[args.workload]()
     h = pbcjk.Handle(system)
     dD = torch.from_numpy(system.D).cuda()
@@ -132,7 +227,8 @@ def main():
     torch.cuda.synchronize()
     print(f"warmup done ({args.warmup} builds)", file=sys.stderr, flush=True)
 
-    lat, gemm_ms, gemm_fl, sfac_ms, n_gemm, sr_fl = [], 0.0, 0.0, 0.0, 0, 0.0
+    lat, gemm_ms, gemm_fl, sfac_ms, n_gemm = [], 0.0, 0.0, 0.0, 0
+    sr_class_ms, sr_terms_class = [0.0] * 21, [0.0] * 21
     stage = {"sr": 0.0, "lr": 0.0, "other": 0.0}
     quartets = terms = 0.0
     torch.cuda.synchronize()
@@ -157,8 +253,9 @@ def main():
         stage["lr"] += st["t_lr_ms"]
         stage["other"] += st["t_other_ms"]
         quartets, terms = st["quartets"], st["terms"]
-        sr_fl += sr_flops(st["terms_class"])
-        n_sr_launch = sum(1 for v in st["terms_class"] if v > 0)
+        for k in range(21):
+            sr_class_ms[k] += st["t_sr_class_ms"][k]
+            sr_terms_class[k] += st["terms_class"][k]
     t_end.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
@@ -168,32 +265,46 @@ def main():
           file=sys.stderr, flush=True)
 
     lat = np.array(lat)
-    achieved = gemm_fl / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else 0.0
-    sr_ms = stage["sr"]
-    sr_ach = sr_fl / (sr_ms * 1e-3) / 1e12 if sr_ms > 0 else 0.0
-    roof_gemm = {
-        "kernel": ("k_dgemm (reciprocal-space K: Y_G = F_G L, K += W_G Y_G Y_G^T, D = L L^T)"
-                   if st["lr_rank"] >= 0 else
-                   "k_dgemm (reciprocal-space K: T_G = F_G D, K += W_G T_G F_G)"),
-        "bound": "mfma", "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-        "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": None,
-        "launches_per_build": n_gemm / args.steps, "avg_launch_ms": gemm_ms / max(1, n_gemm),
-        "kernel_ms_per_build": gemm_ms / args.steps,
-        "flops_per_build": gemm_fl / args.steps,
-    }
-    roof_sr = {
-        "kernel": "k_sr_jk (short-range J/K, all class pairs)",
-        "bound": "alu", "achieved": sr_ach, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-        "frac": sr_ach / FP64_VALU_PEAK_TFLOPS, "traffic": None,
-        "launches_per_build": n_sr_launch,
-        "avg_launch_ms": sr_ms / args.steps / max(1, n_sr_launch),
-        "kernel_ms_per_build": sr_ms / args.steps,
-        "flops_per_build": sr_fl / args.steps,
-    }
-    if roof_sr["kernel_ms_per_build"] >= roof_gemm["kernel_ms_per_build"]:
-        roof, roof2 = roof_sr, roof_gemm
-    else:
-        roof, roof2 = roof_gemm, roof_sr
+    steps = args.steps
+    # GEMM instantiation that formed the reciprocal exchange
+    gk = st["gemm_kernel"]
+    gemm_name = f"k_dgemm<{gk}>"
+    gemm_role = {0: "plain (dense exchange T_G = F_G D, K += W_G T_G F_G; self term)",
+                 1: "low-rank exchange (Y_G = F_G L, K += W_G Y_G Y_G^T, D = L L^T)",
+                 2: "dense exchange after a rejected factor"}[gk]
+    cands = [{
+        "kernel": f"{gemm_name}: {gemm_role}", "name": gemm_name, "bound": "mfma",
+        "ms_per_build": gemm_ms / steps, "flops_per_build": gemm_fl / steps,
+        "launches_per_build": n_gemm / steps, "peak": FP64_MFMA_PEAK_TFLOPS,
+    }]
+    for k in range(21):
+        t = sr_class_ms[k] / steps
+        if t <= 0:
+            continue
+        cb, ck = SLOTS[k]
+        la, lb = CLASSES[cb]
+        lc, ld = CLASSES[ck]
+        coop = (la + lb + lc + ld >= 4) and (cb >= 3 or ck >= 3)
+        name = (f"k_sr_coop<{la}, {lb}, {lc}, {ld}>" if coop else f"k_sr_jk<{la}, {lb}, {lc}, {ld}, ...>")
+        cands.append({
+            "kernel": f"{name}: short-range J/K, class pair ({CLASS_NAMES[cb]}|{CLASS_NAMES[ck]})", "name": name,
+            "bound": "alu", "ms_per_build": t, "flops_per_build": sr_terms_class[k] / steps * sr_flops_per_term(cb, ck),
+            "launches_per_build": 1.0, "peak": FP64_VALU_PEAK_TFLOPS,
+        })
+
+    def roof(c):
+        ach = c["flops_per_build"] / (c["ms_per_build"] * 1e-3) / 1e12 if c["ms_per_build"] > 0 else 0.0
+        return {"kernel": c["kernel"], "bound": c["bound"], "achieved": ach, "peak": c["peak"], "unit": "TFLOP/s",
+                "frac": ach / c["peak"], "traffic": traffic_for(c["name"]),
+                "launches_per_build": c["launches_per_build"],
+                "avg_launch_ms": c["ms_per_build"] / max(1e-9, c["launches_per_build"]),
+                "ms_per_build": c["ms_per_build"], "flops_per_build": c["flops_per_build"]}
+
+    cands.sort(key=lambda c: -c["ms_per_build"])
+    roof_main = roof(cands[0])
+    roof2 = roof(next((c for c in cands[1:] if c["bound"] != cands[0]["bound"]), cands[min(1, len(cands) - 1)]))
+    sr_total_ms = sum(sr_class_ms) / steps
+    sr_total_fl = sum(c["flops_per_build"] for c in cands if c["bound"] == "alu")
     out = {
         "metric": METRIC,
         "value": 1000.0 / ms_per_step,
@@ -223,8 +334,12 @@ def main():
         "stage_ms_per_build": {k: v / args.steps for k, v in stage.items()},
         "E_J": EJ,
         "E_K": EK,
-        "roofline": roof,
+        "roofline": roof_main,
         "roofline_secondary": roof2,
+        "sr_all_classes": {"ms_per_build": sr_total_ms,
+                           "achieved_tflops": sr_total_fl / (sr_total_ms * 1e-3) / 1e12 if sr_total_ms > 0 else 0.0,
+                           "frac_fp64_valu": (sr_total_fl / (sr_total_ms * 1e-3) / 1e12 / FP64_VALU_PEAK_TFLOPS
+                                              if sr_total_ms > 0 else 0.0)},
     }
     h.close()
     if not args.no_cpu_baseline:

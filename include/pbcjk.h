@@ -121,8 +121,11 @@ typedef struct {
     double t_setup_ms;   /* create wall time                                 */
     double t_build_ms;   /* last build wall time                             */
     double t_sr_ms, t_lr_ms, t_other_ms; /* last build, device stage times   */
-    double t_gemm_ms;    /* last build: summed durations of the FP64 matrix-core GEMM launches */
-    double gemm_flops;   /* last build: algorithmic FLOPs of those launches (2 M N K each)     */
+    double t_gemm_ms;    /* last build: summed durations of the launches of the GEMM kernel that
+                            formed the reciprocal exchange (gemm_kernel), self term included
+                            when that kernel is the plain one                                  */
+    double gemm_flops;   /* last build: algorithmic FLOPs of those launches (2 M N K each; the
+                            upper-triangle accumulations count M (M + 1) K)                    */
     int n_gemm;          /* last build: number of those launches                                */
     double t_sfac_ms;    /* last build: summed durations of the structure-factor launches      */
     double terms_class[21]; /* last build: short-range terms per class pair, in the order
@@ -132,7 +135,12 @@ typedef struct {
                                have a term for some density)                            */
     double lr_rank;      /* last build: rank of the density factor used by the reciprocal
                             exchange, or -1 when the dense form was used                */
-    double t_chol_ms;    /* last build: duration of the density factorisation and its check */
+    double t_chol_ms;    /* last build: duration of the density factorisation               */
+    int gemm_kernel;     /* instantiation of t_gemm_ms: 0 k_dgemm<0> (plain), 1 k_dgemm<1>
+                            (low-rank exchange), 2 k_dgemm<2> (dense exchange after a rejected
+                            factor)                                                            */
+    double t_sr_class_ms[21]; /* last build: duration of the short-range launches per class
+                            pair (same order as terms_class)                                   */
 } pbc_jk_counters;
 
 /* Creates a handle: validates and copies the inputs, builds the local pair

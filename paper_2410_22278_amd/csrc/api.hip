@@ -88,8 +88,10 @@ struct pbc_jk {
     // event pairs around GEMM and structure-factor launches of one build
     static constexpr int kMaxTimed = 256;
     std::vector<hipEvent_t> tev;
-    // 0 = GEMM, 1 = structure factors, 2 = low-rank GEMM (flops per unit rank),
-    // 3 = dense GEMM run only when the factor is rejected, 4 = factorisation
+    // 0 = plain GEMM (k_dgemm<0>), 1 = structure factors, 2 = low-rank GEMM
+    // (k_dgemm<1>, flops per unit rank), 3 = dense GEMM run only when the
+    // factor is rejected (k_dgemm<2>), 4 = factorisation, 5 + slot = the
+    // short-range launch of class pair `slot`
     std::vector<int> tkind;
     std::vector<double> tflops;
     int ntimed = 0;
@@ -444,8 +446,10 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
                     a.nbr_bra = !split ? pa.bra : prec ? pa.b32 : pa.b64;
                     a.nbr_ket = !split ? pa.ket : prec ? pa.k32 : pa.k64;
                     a.count = !split ? h->d_ncnt + slot : h->d_wcnt + 2 * slot + prec;
+                    // the FP32 list always sums its shifts in FP64 before the transforms
+                    TimedLaunch tl(h, st, 5 + slot, 0.0);
                     hipError_t e = coop ? launch_sr_coop(cb, ck, a, st)
-                                        : launch_sr_jk(cb, ck, a, prec == 1, h->fold[slot], st);
+                                        : launch_sr_jk(cb, ck, a, prec == 1, prec == 1 || h->fold[slot], st);
                     if (e == hipErrorNotSupported) return fail(PBC_JK_ENOTSUP, "d-shell kernels not built");
                     HIPCHK(e);
                 }
@@ -475,7 +479,10 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
             gr.C = h->d_T; gr.ldc = n; gr.sC = 0;
             gr.nbatch = 1; gr.alpha0 = 1.0; gr.slices = 1;
             gr.ctl = h->d_ctl; gr.ctl_mode = 2;
-            HIPCHK(launch_dgemm(gr, st));
+            {
+                TimedLaunch tg(h, st, 2, 2.0 * (double)n * n);
+                HIPCHK(launch_dgemm(gr, st));
+            }
             HIPCHK(launch_lowrank_check(h->d_Dt, h->d_T, n, h->d_pw, h->d_ctl, st));
         }
         for (int g0 = 0; g0 < nG; g0 += h->gchunk) {
@@ -566,10 +573,17 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
             g1.B = h->d_Dt; g1.ldb = n; g1.sB = 0;
             g1.C = h->d_T; g1.ldc = n; g1.sC = 0;
             g1.nbatch = 1; g1.alpha0 = 1.0; g1.reduce = 0; g1.slices = 1;
-            HIPCHK(launch_dgemm(g1, st));
+            const double nd = (double)n;
+            {
+                TimedLaunch tg(h, st, 0, 2.0 * nd * nd * nd);
+                HIPCHK(launch_dgemm(g1, st));
+            }
             GemmArgs g2 = g1;
             g2.A = h->d_T; g2.B = h->d_S; g2.C = h->d_Kt; g2.alpha0 = f; g2.reduce = 1; g2.upper = 1;
-            HIPCHK(launch_dgemm(g2, st));
+            {
+                TimedLaunch tg(h, st, 0, nd * (nd + 1.0) * nd);
+                HIPCHK(launch_dgemm(g2, st));
+            }
         }
     }
 
@@ -817,13 +831,17 @@ int pbc_jk_stats(const pbc_jk *hc, pbc_jk_counters *out)
         if (h->lr_ran) HIPCHK(hipMemcpy(ctl, h->d_ctl, sizeof ctl, hipMemcpyDeviceToHost));
         const bool dense = !h->lr_ran || ctl[1];
         h->st.lr_rank = dense ? -1.0 : (double)ctl[0];
+        // the GEMM figures describe the instantiation that did the exchange
+        const int main_kind = !h->lr_ran ? 0 : dense ? 3 : 2;
+        h->st.gemm_kernel = main_kind == 0 ? 0 : main_kind == 2 ? 1 : 2;
         h->st.t_gemm_ms = h->st.t_sfac_ms = h->st.gemm_flops = h->st.t_chol_ms = 0.0;
         h->st.n_gemm = 0;
+        for (int k = 0; k < 21; ++k) h->st.t_sr_class_ms[k] = 0.0;
         for (int i = 0; i < h->ntimed; ++i) {
             float ms = 0;
             HIPCHK(hipEventElapsedTime(&ms, h->tev[2 * i], h->tev[2 * i + 1]));
             const int kind = h->tkind[i];
-            if (kind == 0 || (kind == 2 && !dense) || (kind == 3 && dense)) {
+            if (kind == main_kind) {
                 h->st.t_gemm_ms += ms;
                 h->st.gemm_flops += h->tflops[i] * (kind == 2 ? (double)ctl[0] : 1.0);
                 h->st.n_gemm++;
@@ -831,6 +849,8 @@ int pbc_jk_stats(const pbc_jk *hc, pbc_jk_counters *out)
                 h->st.t_sfac_ms += ms;
             } else if (kind == 4) {
                 h->st.t_chol_ms += ms;
+            } else if (kind >= 5) {
+                h->st.t_sr_class_ms[kind - 5] += ms;
             }
         }
     }

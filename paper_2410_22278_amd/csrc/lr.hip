@@ -258,6 +258,10 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs a)
 // B[l >> 4][l & 15]; result register r holds D[(l >> 4) + 4 r][l & 15].
 constexpr int GBM = 128, GBN = 128, GBK = 16, GPAD = 2;
 
+// GATE (separate instantiations, so that profiles tell the roles apart):
+// 0 plain, 1 low-rank exchange (ctl modes 1, 2), 2 dense exchange gated on
+// the factor being rejected (ctl mode 3).
+template <int GATE>
 __global__ __launch_bounds__(256) void k_dgemm(GemmArgs g)
 {
     __shared__ double As[GBK][GBM + GPAD];
@@ -402,7 +406,7 @@ __global__ __launch_bounds__(256) void k_dgemm(GemmArgs g)
 // remaining diagonal d_i -= L_ik^2, with its block maximum for step k + 1.
 // Work layout: diag[n] | pv[2][nblk] | stop, max0; wi: pi[2][nblk].
 constexpr int kCholRows = 64;
-constexpr int kCholSingleMax = 2048;   // one-workgroup factorisation up to this n
+constexpr int kCholSingleMax = 256;    // one-workgroup factorisation up to this n
 
 __device__ inline void argmax_merge(double &v, int &i, double ov, int oi)
 {
@@ -692,7 +696,9 @@ hipError_t launch_dgemm(const GemmArgs &a, hipStream_t st)
     if (a.M <= 0 || a.N <= 0 || a.K <= 0 || a.nbatch <= 0) return hipSuccess;
     int z = a.reduce ? a.slices : a.nbatch;
     dim3 grid((a.N + GBN - 1) / GBN, (a.M + GBM - 1) / GBM, z);
-    hipLaunchKernelGGL(k_dgemm, grid, dim3(256), 0, st, a);
+    if (a.ctl_mode == 0) hipLaunchKernelGGL(k_dgemm<0>, grid, dim3(256), 0, st, a);
+    else if (a.ctl_mode == 3) hipLaunchKernelGGL(k_dgemm<2>, grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL(k_dgemm<1>, grid, dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

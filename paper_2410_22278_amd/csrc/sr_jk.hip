@@ -205,17 +205,20 @@ __global__ __launch_bounds__(256) void k_sr_jk(SRArgs a)
                     for (int i3 = 0; i3 < ND; ++i3) acc[i0][i1][i2][i3] = 0.0;
         unsigned long long ent_terms = 0;
         // group-level density screen (already applied when the list was compacted)
-        const int pb_end = (gb.Qmax * gk.Qmax * wD > a.d_schwarz) ? gb.pend : gb.pstart;
 
-        for (int pb = gb.pstart; pb < pb_end; ++pb) {
-            const PairRec Pb = a.pairs[pb];
-            EAxis<LA, LB> Ex, Ey, Ez;
-            const double hb = 0.5 / Pb.p;
-            herm_axis<LA, LB>(hb, Pb.PA[0], Pb.PB[0], Ex);
-            herm_axis<LA, LB>(hb, Pb.PA[1], Pb.PB[1], Ey);
-            herm_axis<LA, LB>(hb, Pb.PA[2], Pb.PB[2], Ez);
-            for (int pk = gk.pstart; pk < gk.pend; ++pk) {
-                const PairRec Pk = a.pairs[pk];
+        // ket pairs outer (each lane reads its own ket records once), bra pairs
+        // inner (the wavefront's lanes mostly share the bra group, so those
+        // loads are broadcast from cache)
+        const int pk_end = (gb.Qmax * gk.Qmax * wD > a.d_schwarz) ? gk.pend : gk.pstart;
+        for (int pk = gk.pstart; pk < pk_end; ++pk) {
+            const PairRec Pk = a.pairs[pk];
+            EAxis<LC, LD> Fx, Fy, Fz;
+            const double hk = 0.5 / Pk.p;
+            herm_axis<LC, LD>(hk, Pk.PA[0], Pk.PB[0], Fx);
+            herm_axis<LC, LD>(hk, Pk.PA[1], Pk.PB[1], Fy);
+            herm_axis<LC, LD>(hk, Pk.PA[2], Pk.PB[2], Fz);
+            for (int pb = gb.pstart; pb < gb.pend; ++pb) {
+                const PairRec Pb = a.pairs[pb];
                 if (!(Pb.Q * Pk.Q * wD > a.d_schwarz)) continue;
                 ++cnt_q;
                 double rad2;
@@ -223,11 +226,11 @@ __global__ __launch_bounds__(256) void k_sr_jk(SRArgs a)
                 const double p = Pb.p, q = Pk.p, pq = p * q;
                 const double rho = pq / (p + q);
                 const double pref = Pb.cpre * Pk.cpre * kTwoPi52 / (pq * sqrt(p + q));
-                EAxis<LC, LD> Fx, Fy, Fz;
-                const double hk = 0.5 / q;
-                herm_axis<LC, LD>(hk, Pk.PA[0], Pk.PB[0], Fx);
-                herm_axis<LC, LD>(hk, Pk.PA[1], Pk.PB[1], Fy);
-                herm_axis<LC, LD>(hk, Pk.PA[2], Pk.PB[2], Fz);
+                EAxis<LA, LB> Ex, Ey, Ez;
+                const double hb = 0.5 / p;
+                herm_axis<LA, LB>(hb, Pb.PA[0], Pb.PB[0], Ex);
+                herm_axis<LA, LB>(hb, Pb.PA[1], Pb.PB[1], Ey);
+                herm_axis<LA, LB>(hb, Pb.PA[2], Pb.PB[2], Ez);
                 const double cen[3] = {Pb.P[0] - Pk.P[0], Pb.P[1] - Pk.P[1], Pb.P[2] - Pk.P[2]};
                 if (FOLD) {
                     // lattice sum of the Hermite integrals in FP64, one transform

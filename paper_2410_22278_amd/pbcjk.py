@@ -59,7 +59,8 @@ class pbc_jk_counters(ctypes.Structure):
                 ("t_build_ms", c_double), ("t_sr_ms", c_double), ("t_lr_ms", c_double),
                 ("t_other_ms", c_double), ("t_gemm_ms", c_double), ("gemm_flops", c_double),
                 ("n_gemm", c_int), ("t_sfac_ms", c_double), ("terms_class", c_double * 21),
-                ("n_group_pairs", c_double), ("lr_rank", c_double), ("t_chol_ms", c_double)]
+                ("n_group_pairs", c_double), ("lr_rank", c_double), ("t_chol_ms", c_double),
+                ("gemm_kernel", c_int), ("t_sr_class_ms", c_double * 21)]
 
 
 class pbc_jk_server_config(ctypes.Structure):
@@ -234,6 +235,7 @@ def pbc_jk_stats(h: int) -> dict:
     _check(load().pbc_jk_stats(c_void_p(h), byref(s)))
     out = {k: getattr(s, k) for k, _ in s._fields_}
     out["terms_class"] = list(s.terms_class)
+    out["t_sr_class_ms"] = list(s.t_sr_class_ms)
     return out
 
 
