@@ -25,6 +25,8 @@ FP64_VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 CLASSES = [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2)]
 CLASS_NAMES = ["ss", "ps", "pp", "ds", "dp", "dd"]
 SLOTS = [(cb, ck) for cb in range(6) for ck in range(cb, 6)]
+# class pairs run by the cooperative (one wavefront per group pair) kernel
+COOP_SLOTS = {(0, 5), (1, 5), (2, 4), (2, 5), (3, 4), (3, 5), (4, 4), (4, 5), (5, 5)}
 CSRC = os.path.join(ROOT, "paper_2410_22278_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
@@ -284,7 +286,7 @@ def main():
         cb, ck = SLOTS[k]
         la, lb = CLASSES[cb]
         lc, ld = CLASSES[ck]
-        coop = (la + lb + lc + ld >= 4) and (cb >= 3 or ck >= 3)
+        coop = (cb, ck) in COOP_SLOTS
         name = (f"k_sr_coop<{la}, {lb}, {lc}, {ld}>" if coop else f"k_sr_jk<{la}, {lb}, {lc}, {ld}, ...>")
         cands.append({
             "kernel": f"{name}: short-range J/K, class pair ({CLASS_NAMES[cb]}|{CLASS_NAMES[ck]})", "name": name,

@@ -180,6 +180,13 @@ int pbc_jk_stats(const pbc_jk *h, pbc_jk_counters *out);
 #define PBC_JK_PART_SELF 4
 int pbc_jk_set_parts(pbc_jk *h, int mask);
 
+/* Restricts the real-space part to the class pairs whose bits are set in
+ * mask21 (bit k = k-th (bra class, ket class) pair in the order of
+ * terms_class; default all 21).  For per-class testing and for timing a
+ * large cell one class pair at a time.  EINVAL for a NULL handle or bits
+ * above 2^21. */
+int pbc_jk_set_sr_classes(pbc_jk *h, int mask21);
+
 /* Form of the reciprocal exchange K_LR = sum_G W_G (A_G D A_G + B_G D B_G)
  * (Sec. 2.4; A, B the real and imaginary pair structure factors):
  *   PBC_JK_LR_AUTO  (default) factor D = L L^T by pivoted Cholesky on the

@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpbcjk.so")
 OBJDIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["setup.cpp", "sr_jk.hip", "sr_coop.hip", "nbr.hip", "lr.hip", "api.hip", "server.cpp"]
+SOURCES = ["sr_slice_dp.hip", "sr_slice.hip", "sr_jk.hip", "sr_coop.hip", "setup.cpp", "nbr.hip", "lr.hip", "api.hip", "server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

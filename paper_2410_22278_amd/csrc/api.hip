@@ -20,8 +20,20 @@ namespace {
 
 constexpr int kClassL[kNumClass] = {0, 1, 2, 2, 3, 4};
 constexpr int kNumCounters = 48;     // see SRArgs::counters
+
+// Class pairs (cb <= ck) with a per-lane register kernel: everything without
+// a d shell, and the d pairs (ds|ss), (dp|ss), (ds|ps), (dp|ps), (ds|pp), (ds|ds).
+bool sr_per_lane(int cb, int ck)
+{
+    if (cb < 3 && ck < 3) return true;
+    const int lo = cb < ck ? cb : ck, hi = cb < ck ? ck : cb;
+    return (lo == 0 && (hi == 3 || hi == 4)) || (lo == 1 && (hi == 3 || hi == 4)) || (lo == 2 && hi == 3) ||
+           (lo == 3 && hi == 3);
+}
 constexpr double kFoldRmin = 20.0;   // bohr: cells with a shorter lattice vector start folded
-constexpr double kFoldRatio = 1.5;   // shifts per quartet above which the lattice sum is folded
+constexpr double kFoldRatio = 1.1;   // shifts per quartet above which the lattice sum is folded
+constexpr double kCoopRatio = 4.5;   // shifts per quartet above which large d pairs use one
+                                     // wavefront per group pair (it evaluates each shift once)
 
 thread_local std::string g_err;
 
@@ -50,6 +62,7 @@ struct pbc_jk {
     size_t dry_bytes = 0;
     int parts = PBC_JK_PART_SR | PBC_JK_PART_LR | PBC_JK_PART_SELF;
     int lr_mode = PBC_JK_LR_AUTO;
+    int sr_classes = (1 << 21) - 1;
     double lr_tol = 1e-13;
     hipStream_t own = nullptr;
     // setup data
@@ -83,6 +96,8 @@ struct pbc_jk {
     unsigned long long *h_cnt = nullptr;
     hipEvent_t ev_cnt = nullptr;
     bool fold[21] = {false};
+    int class_max_pp[6] = {0};   // most primitive pairs in one group, per class
+    bool coop_d[21] = {false};   // large d class pairs: one wavefront per group pair (else slices)
     int gchunk = 0;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     // event pairs around GEMM and structure-factor launches of one build
@@ -267,6 +282,11 @@ int create_device(pbc_jk *h)
     if ((rc = dalloc(h, &h->d_scal, 4))) return rc;
     if ((rc = dalloc(h, &h->d_dmaxg, 1))) return rc;
     if ((rc = dalloc(h, &h->d_cnt, kNumCounters))) return rc;
+    for (int c = 0; c < kNumClass; ++c) {
+        h->class_max_pp[c] = 0;
+        for (int g = S.class_start[c]; g < S.class_start[c + 1]; ++g)
+            h->class_max_pp[c] = std::max(h->class_max_pp[c], S.groups[g].pend - S.groups[g].pstart);
+    }
     if (!h->dry) {
         if (!h->h_cnt) HIPCHK(hipHostMalloc((void **)&h->h_cnt, kNumCounters * sizeof(unsigned long long)));
         std::memset(h->h_cnt, 0, kNumCounters * sizeof(unsigned long long));
@@ -400,7 +420,10 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
     if (h->ev_cnt && hipEventQuery(h->ev_cnt) == hipSuccess)
         for (int k = 0; k < 21; ++k) {
             const double nq = (double)h->h_cnt[24 + k], nt = (double)h->h_cnt[2 + k];
-            if (nq > 0) h->fold[k] = nt > kFoldRatio * nq;
+            if (nq > 0) {
+                h->fold[k] = nt > kFoldRatio * nq;
+                h->coop_d[k] = nt > kCoopRatio * nq;
+            }
         }
 
     // B3/B4: short-range J and K.  Per class pair: the density-weighted
@@ -421,9 +444,10 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
         for (int cb = 0; cb < kNumClass; ++cb)
             for (int ck = cb; ck < kNumClass; ++ck, ++slot) {
                 const long e0 = h->nbr_off[slot], e1 = h->nbr_off[slot + 1];
-                if (e1 == e0) continue;
-                // class pairs with a d shell and L >= 4 use one wavefront per group pair (FP64)
-                const bool coop = (kClassL[cb] + kClassL[ck] >= 4) && (cb >= 3 || ck >= 3);
+                if (e1 == e0 || !((h->sr_classes >> slot) & 1)) continue;
+                // d class pairs whose block does not fit in one lane's registers use
+                // one wavefront per group pair (FP64)
+                const bool coop = !sr_per_lane(cb, ck);
                 // mixed precision: the density screen splits the list into FP64
                 // and FP32 work lists; otherwise the kernels screen in place
                 const bool split = S.fp32_below > 0 && !coop;
@@ -442,14 +466,18 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
                 a.gk0 = S.class_start[ck];
                 a.tri = (cb == ck);
                 a.max_entries = e1 - e0;
+                a.max_prim_pairs = std::max(h->class_max_pp[cb], h->class_max_pp[ck]);
                 for (int prec = 0; prec < (split ? 2 : 1); ++prec) {
                     a.nbr_bra = !split ? pa.bra : prec ? pa.b32 : pa.b64;
                     a.nbr_ket = !split ? pa.ket : prec ? pa.k32 : pa.k64;
                     a.count = !split ? h->d_ncnt + slot : h->d_wcnt + 2 * slot + prec;
                     // the FP32 list always sums its shifts in FP64 before the transforms
                     TimedLaunch tl(h, st, 5 + slot, 0.0);
-                    hipError_t e = coop ? launch_sr_coop(cb, ck, a, st)
-                                        : launch_sr_jk(cb, ck, a, prec == 1, prec == 1 || h->fold[slot], st);
+                    hipError_t e;
+                    if (!coop) e = launch_sr_jk(cb, ck, a, prec == 1, h->fold[slot], st);
+                    else if (!h->coop_d[slot]) e = launch_sr_slices(cb, ck, a, h->fold[slot], st);
+                    else e = hipErrorNotSupported;
+                    if (e == hipErrorNotSupported && coop) e = launch_sr_coop(cb, ck, a, st);
                     if (e == hipErrorNotSupported) return fail(PBC_JK_ENOTSUP, "d-shell kernels not built");
                     HIPCHK(e);
                 }
@@ -798,6 +826,14 @@ int pbc_jk_set_lr(pbc_jk *h, int mode, double tol)
     if (!(tol < 1.0)) return fail(PBC_JK_EINVAL, "tolerance must be below 1");
     h->lr_mode = mode;
     if (tol > 0.0) h->lr_tol = tol;
+    return 0;
+}
+
+int pbc_jk_set_sr_classes(pbc_jk *h, int mask21)
+{
+    if (!h) return fail(PBC_JK_EINVAL, "handle is NULL");
+    if (mask21 < 0 || mask21 >= (1 << 21)) return fail(PBC_JK_EINVAL, "class-pair mask has bits above 2^21");
+    h->sr_classes = mask21;
     return 0;
 }
 

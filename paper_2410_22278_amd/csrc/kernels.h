@@ -16,6 +16,7 @@ struct SRArgs {
                           //   neighbour list in one precision
     const unsigned long long *count;   // device: entries in the work list
     long max_entries;     // host: upper bound of *count (sizes the grid)
+    int max_prim_pairs;   // host: most primitive pairs in one group of either class
     const double *Dt;     // scaled Cartesian density, nbfc x nbfc
     const double *Dmax;   // nshell x nshell block maxima of the Cartesian density
     double *X, *Y;        // J and K halves, nbfc x nbfc
@@ -66,6 +67,9 @@ struct PartArgs {
 hipError_t launch_partition(const PartArgs &a, hipStream_t st);
 
 hipError_t launch_sr_jk(int cb, int ck, const SRArgs &a, bool f32, bool fold, hipStream_t st);
+// large d class pairs in the per-lane kernel, one launch per component slice
+hipError_t launch_sr_slices(int cb, int ck, const SRArgs &a, bool fold, hipStream_t st);
+hipError_t launch_sr_slices_dp(int cb, int ck, const SRArgs &a, bool fold, hipStream_t st);
 // class pairs with total angular momentum >= 5 (one wavefront per group pair)
 hipError_t launch_sr_coop(int cb, int ck, const SRArgs &a, hipStream_t st);
 

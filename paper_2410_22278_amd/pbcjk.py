@@ -27,7 +27,7 @@ LR_AUTO, LR_DENSE = 0, 1
 
 # every symbol the header declares
 EXPORTS = ["pbc_jk_create", "pbc_jk_build", "pbc_jk_build_device", "pbc_jk_destroy",
-           "pbc_jk_nbf", "pbc_jk_stats", "pbc_jk_set_parts", "pbc_jk_set_lr", "pbc_jk_last_error",
+           "pbc_jk_nbf", "pbc_jk_stats", "pbc_jk_set_parts", "pbc_jk_set_sr_classes", "pbc_jk_set_lr", "pbc_jk_last_error",
            "pbc_jk_server_create", "pbc_jk_server_submit", "pbc_jk_server_wait", "pbc_jk_server_cancel",
            "pbc_jk_server_stats", "pbc_jk_server_destroy"]
 
@@ -115,6 +115,8 @@ def load():
     lib.pbc_jk_stats.restype = c_int
     lib.pbc_jk_set_parts.argtypes = [c_void_p, c_int]
     lib.pbc_jk_set_parts.restype = c_int
+    lib.pbc_jk_set_sr_classes.argtypes = [c_void_p, c_int]
+    lib.pbc_jk_set_sr_classes.restype = c_int
     lib.pbc_jk_set_lr.argtypes = [c_void_p, c_int, c_double]
     lib.pbc_jk_set_lr.restype = c_int
     lib.pbc_jk_server_create.argtypes = [POINTER(pbc_jk_server_config), POINTER(c_void_p)]
@@ -268,6 +270,9 @@ class Handle:
 
     def set_parts(self, mask):
         pbc_jk_set_parts(self.h, mask)
+
+    def set_sr_classes(self, mask21):
+        _check(load().pbc_jk_set_sr_classes(c_void_p(self.h), int(mask21)))
 
     def set_lr(self, mode, tol=0.0):
         pbc_jk_set_lr(self.h, mode, tol)

@@ -72,5 +72,6 @@ def test_null_handle_calls():
     assert lib.pbc_jk_nbf(None) == pbcjk.PBC_JK_EINVAL
     assert lib.pbc_jk_set_parts(None, 1) == pbcjk.PBC_JK_EINVAL
     assert lib.pbc_jk_set_lr(None, pbcjk.LR_DENSE, 0.0) == pbcjk.PBC_JK_EINVAL
+    assert lib.pbc_jk_set_sr_classes(None, 1) == pbcjk.PBC_JK_EINVAL
     lib.pbc_jk_destroy(None)   # NULL-safe
     assert lib.pbc_jk_build(None, None, None, None, None, None) == pbcjk.PBC_JK_EINVAL

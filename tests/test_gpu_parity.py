@@ -212,3 +212,21 @@ def test_d_mixed(lib, oracle_mod):
     dJ, dK, dEJ, dEK = _report(f"d mixed (fp32 {st['terms_fp32']:.0f}/{st['terms']:.0f})", J, K, ref, s.natom,
                                EJ, EK)
     assert dJ < 1e-7 and dK < 1e-7 and dEJ < 1e-6 and dEK < 1e-6
+
+
+def test_d_kernel_choice_over_builds(lib, oracle_mod):
+    """Repeated builds of one d-shell cell: the first runs the large d class
+    pairs in component slices, later ones choose per class pair from the
+    previous build's shifts per quartet (this small cell has many, so the
+    one-wavefront-per-group-pair kernel takes over) and fold the lattice
+    sums.  Every build must match the oracle."""
+    case = D_CASES[0]
+    s = inputs.small_cell(**case)
+    ref = oracle_mod.jk(s)
+    with lib.Handle(s) as h:
+        for k in range(3):
+            J, K, EJ, EK = h.build(s.D)
+            st = h.stats()
+            ratio = st["terms"] / max(1.0, st["quartets"])
+            dJ, dK, dEJ, dEK = _report(f"d build {k} (shifts/quartet {ratio:.1f})", J, K, ref, s.natom, EJ, EK)
+            assert dJ < 1e-9 and dK < 1e-9 and dEJ < 1e-9 and dEK < 1e-9
