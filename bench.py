@@ -230,6 +230,7 @@ def main():
     print(f"warmup done ({args.warmup} builds)", file=sys.stderr, flush=True)
 
     lat, gemm_ms, gemm_fl, sfac_ms, n_gemm = [], 0.0, 0.0, 0.0, 0
+    blas_ms, blas_fl, n_blas = 0.0, 0.0, 0
     sr_class_ms, sr_terms_class = [0.0] * 21, [0.0] * 21
     stage = {"sr": 0.0, "lr": 0.0, "other": 0.0}
     quartets = terms = 0.0
@@ -248,6 +249,9 @@ def main():
         e1.synchronize()
         lat.append(e0.elapsed_time(e1))
         gemm_ms += st["t_gemm_ms"]
+        blas_ms += st["t_blas_ms"]
+        blas_fl += st["blas_flops"]
+        n_blas += st["n_blas"]
         gemm_fl += st["gemm_flops"]
         n_gemm += st["n_gemm"]
         sfac_ms += st["t_sfac_ms"]
@@ -271,14 +275,19 @@ def main():
     # GEMM instantiation that formed the reciprocal exchange
     gk = st["gemm_kernel"]
     gemm_name = f"k_dgemm<{gk}>"
-    gemm_role = {0: "plain (dense exchange T_G = F_G D, K += W_G T_G F_G; self term)",
-                 1: "low-rank exchange (Y_G = F_G L, K += W_G Y_G Y_G^T, D = L L^T)",
-                 2: "dense exchange after a rejected factor"}[gk]
+    gemm_role = {0: "dense exchange T_G = F_G D, K += W_G T_G F_G, and the self term",
+                 1: "low-rank exchange accumulation K += W_G Y_G Y_G^T (D = L L^T) and the factor's residual check"}[gk]
     cands = [{
         "kernel": f"{gemm_name}: {gemm_role}", "name": gemm_name, "bound": "mfma",
         "ms_per_build": gemm_ms / steps, "flops_per_build": gemm_fl / steps,
         "launches_per_build": n_gemm / steps, "peak": FP64_MFMA_PEAK_TFLOPS,
     }]
+    if blas_ms > 0:
+        cands.append({
+            "kernel": "rocBLAS dgemm_strided_batched: Y_G = F_G L", "name": "rocblas_dgemm_strided_batched",
+            "bound": "mfma", "ms_per_build": blas_ms / steps, "flops_per_build": blas_fl / steps,
+            "launches_per_build": n_blas / steps, "peak": FP64_MFMA_PEAK_TFLOPS,
+        })
     for k in range(21):
         t = sr_class_ms[k] / steps
         if t <= 0:

@@ -136,11 +136,14 @@ typedef struct {
     double lr_rank;      /* last build: rank of the density factor used by the reciprocal
                             exchange, or -1 when the dense form was used                */
     double t_chol_ms;    /* last build: duration of the density factorisation               */
-    int gemm_kernel;     /* instantiation of t_gemm_ms: 0 k_dgemm<0> (plain), 1 k_dgemm<1>
-                            (low-rank exchange), 2 k_dgemm<2> (dense exchange after a rejected
-                            factor)                                                            */
+    int gemm_kernel;     /* instantiation of t_gemm_ms: 0 k_dgemm<0> (dense exchange and self
+                            term), 1 k_dgemm<1> (low-rank accumulation K += W Y Y^T and the
+                            residual check of the factor)                                      */
     double t_sr_class_ms[21]; /* last build: duration of the short-range launches per class
                             pair (same order as terms_class)                                   */
+    double t_blas_ms;    /* last build: duration of the rocBLAS products Y = F L (low rank)    */
+    double blas_flops;   /* last build: their FLOPs (2 n^2 rank per F matrix)                  */
+    int n_blas;          /* last build: number of those rocBLAS calls                          */
 } pbc_jk_counters;
 
 /* Creates a handle: validates and copies the inputs, builds the local pair
@@ -195,8 +198,9 @@ int pbc_jk_set_sr_classes(pbc_jk *h, int mask21);
  *                   with Y = A_G L and B_G L; the factor is accepted only if
  *                   max |D - L L^T| <= 2 tol max diag(D) + 4 n eps max diag(D)
  *                   and its rank is at most 3/4 of the Cartesian AO count,
- *                   otherwise the dense form runs.  The choice is made on the
- *                   device per build (no host synchronisation).
+ *                   otherwise the dense form runs.  The build reads the
+ *                   factor's rank back once (the stream is synchronised
+ *                   there).
  *   PBC_JK_LR_DENSE always the dense form T_G = A_G D, K_LR += W_G T_G A_G.
  * tol <= 0 keeps the current tolerance (default 1e-13).  EINVAL for an
  * unknown mode or a NULL handle. */

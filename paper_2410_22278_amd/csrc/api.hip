@@ -1,5 +1,6 @@
 // C ABI of the periodic J/K library (see include/pbcjk.h).
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <chrono>
@@ -82,6 +83,8 @@ struct pbc_jk {
     // low-rank reciprocal exchange: density factor (by columns), work, control
     double *d_L = nullptr, *d_pw = nullptr;
     int *d_pwi = nullptr, *d_ctl = nullptr;
+    int *h_ctl = nullptr;        // pinned copy of the control block
+    int last_rslot = 0;          // timed-launch slot of the residual check
     int lr_rmax = 0;
     bool lr_ran = false;
     size_t nbr_bytes_needed = 0;   // set once the neighbour lists are counted
@@ -103,10 +106,10 @@ struct pbc_jk {
     // event pairs around GEMM and structure-factor launches of one build
     static constexpr int kMaxTimed = 256;
     std::vector<hipEvent_t> tev;
-    // 0 = plain GEMM (k_dgemm<0>), 1 = structure factors, 2 = low-rank GEMM
-    // (k_dgemm<1>, flops per unit rank), 3 = dense GEMM run only when the
-    // factor is rejected (k_dgemm<2>), 4 = factorisation, 5 + slot = the
-    // short-range launch of class pair `slot`
+    // 0 = plain GEMM (k_dgemm<0>), 1 = structure factors, 2 = low-rank
+    // accumulation and its residual check (k_dgemm<1>), 4 = factorisation,
+    // 5 + slot = the short-range launch of class pair `slot` (5..25),
+    // 30 = the rocBLAS products Y = F L
     std::vector<int> tkind;
     std::vector<double> tflops;
     int ntimed = 0;
@@ -194,6 +197,8 @@ void release(pbc_jk *h)
     h->ev_cnt = nullptr;
     if (h->h_cnt) (void)hipHostFree(h->h_cnt);
     h->h_cnt = nullptr;
+    if (h->h_ctl) (void)hipHostFree(h->h_ctl);
+    h->h_ctl = nullptr;
     if (h->own) (void)hipStreamDestroy(h->own);
     h->own = nullptr;
     for (auto &e : h->ev) e = nullptr;
@@ -289,6 +294,8 @@ int create_device(pbc_jk *h)
     }
     if (!h->dry) {
         if (!h->h_cnt) HIPCHK(hipHostMalloc((void **)&h->h_cnt, kNumCounters * sizeof(unsigned long long)));
+        if (!h->h_ctl) HIPCHK(hipHostMalloc((void **)&h->h_ctl, 4 * sizeof(int)));
+        std::memset(h->h_ctl, 0, 4 * sizeof(int));
         std::memset(h->h_cnt, 0, kNumCounters * sizeof(unsigned long long));
         if (!h->ev_cnt) HIPCHK(hipEventCreateWithFlags(&h->ev_cnt, hipEventDisableTiming));
         // first guess: quartets of small cells have several lattice shifts
@@ -391,6 +398,37 @@ int build_neighbours(pbc_jk *h)
     unsigned long long seg[21];
     for (int k = 0; k < 21; ++k) seg[k] = (unsigned long long)(h->nbr_off[k + 1] - h->nbr_off[k]);
     HIPCHK(hipMemcpy(h->d_ncnt, seg, sizeof seg, hipMemcpyHostToDevice));
+    return 0;
+}
+
+// One rocBLAS handle per host thread (rocBLAS handles are not shared between
+// threads), created on first use and kept for the thread's lifetime.
+rocblas_handle thread_blas()
+{
+    struct Holder {
+        rocblas_handle h = nullptr;
+        ~Holder()
+        {
+            if (h) (void)rocblas_destroy_handle(h);
+        }
+    };
+    thread_local Holder holder;
+    if (!holder.h && rocblas_create_handle(&holder.h) != rocblas_status_success) holder.h = nullptr;
+    return holder.h;
+}
+
+// Y_b = F_b L for b < nb (column-major: F_b n x n, L n x rank with ld n,
+// Y_b n x rank with ld n, stored one after another in d_T).
+int blas_lowrank_stage1(pbc_jk *h, hipStream_t st, int n, int rank, int nb)
+{
+    rocblas_handle bh = thread_blas();
+    if (!bh) return fail(PBC_JK_EDEVICE, "rocblas_create_handle failed");
+    if (rocblas_set_stream(bh, st) != rocblas_status_success) return fail(PBC_JK_EDEVICE, "rocblas_set_stream failed");
+    const double one = 1.0, zero = 0.0;
+    const rocblas_status rs = rocblas_dgemm_strided_batched(
+        bh, rocblas_operation_none, rocblas_operation_none, n, rank, n, &one, h->d_F, n, (rocblas_stride)n * n,
+        h->d_L, n, 0, &zero, h->d_T, n, (rocblas_stride)n * rank, nb);
+    if (rs != rocblas_status_success) return fail(PBC_JK_EDEVICE, "rocblas_dgemm_strided_batched failed");
     return 0;
 }
 
@@ -507,12 +545,19 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
             gr.C = h->d_T; gr.ldc = n; gr.sC = 0;
             gr.nbatch = 1; gr.alpha0 = 1.0; gr.slices = 1;
             gr.ctl = h->d_ctl; gr.ctl_mode = 2;
+            h->last_rslot = h->ntimed;
             {
-                TimedLaunch tg(h, st, 2, 2.0 * (double)n * n);
+                TimedLaunch tg(h, st, 2, 0.0);
                 HIPCHK(launch_dgemm(gr, st));
             }
             HIPCHK(launch_lowrank_check(h->d_Dt, h->d_T, n, h->d_pw, h->d_ctl, st));
+            // the factor's rank sizes the products below: read it back
+            HIPCHK(hipMemcpyAsync(h->h_ctl, h->d_ctl, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
         }
+        const bool use_lr = lowrank && !h->h_ctl[1];
+        const int rank = use_lr ? h->h_ctl[0] : 0;
+        if (lowrank && h->profile && h->last_rslot < h->ntimed) h->tflops[h->last_rslot] = 2.0 * (double)n * n * h->h_ctl[0];
         for (int g0 = 0; g0 < nG; g0 += h->gchunk) {
             const int gc = std::min(h->gchunk, nG - g0);
             HIPCHK(launch_fill(h->d_F, 2L * gc * n2, 0.0, st));
@@ -531,55 +576,49 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
             }
             if (wantK) {
                 const double nd = (double)n;
-                if (lowrank) {
-                    // Y_b = F_b L (n x rank), then K += W_b Y_b Y_b^T on the upper tiles
-                    GemmArgs g1{};
-                    g1.M = n; g1.N = rmax; g1.K = n;
-                    g1.A = h->d_F; g1.lda = n; g1.sA = n2;
-                    g1.B = h->d_L; g1.ldb = n; g1.sB = 0; g1.transB = 1;
-                    g1.C = h->d_T; g1.ldc = rmax; g1.sC = (long)n * rmax;
-                    g1.nbatch = 2 * gc; g1.alpha0 = 1.0; g1.slices = 1;
-                    g1.ctl = h->d_ctl; g1.ctl_mode = 1;
+                if (use_lr && rank > 0) {
+                    // Y_b = F_b L (rocBLAS, column-major: Y_b is n x rank, ld n), then
+                    // K += W_b Y_b Y_b^T on the upper output tiles
                     {
-                        TimedLaunch tl(h, st, 2, 2.0 * nd * nd * g1.nbatch);
+                        TimedLaunch tl(h, st, 30, 2.0 * nd * nd * rank * 2 * gc);
+                        const int brc = blas_lowrank_stage1(h, st, n, rank, 2 * gc);
+                        if (brc) return brc;
+                    }
+                    for (int half = 0; half < 2; ++half) {
+                        GemmArgs g2{};
+                        g2.M = g2.N = n; g2.K = rank;
+                        g2.A = h->d_T + (long)half * gc * n * rank; g2.lda = n; g2.sA = (long)n * rank; g2.transA = 1;
+                        g2.B = g2.A; g2.ldb = n; g2.sB = (long)n * rank;
+                        g2.C = h->d_Kt; g2.ldc = n; g2.sC = 0;
+                        g2.nbatch = gc; g2.alpha = h->d_Gw + g0; g2.alpha0 = 1.0; g2.reduce = 1; g2.upper = 1;
+                        g2.slices = std::max(1, std::min(gc, 2048 / std::max(1, upper_tiles)));
+                        g2.tag = 1;
+                        TimedLaunch tl(h, st, 2, nd * (nd + 1.0) * rank * g2.nbatch);
+                        HIPCHK(launch_dgemm(g2, st));
+                    }
+                } else if (!use_lr) {
+                    // dense form: T_b = F_b D, K += W_b T_b F_b on the upper tiles (F_b symmetric)
+                    GemmArgs g1{};
+                    g1.M = g1.N = g1.K = n;
+                    g1.A = h->d_F; g1.lda = n; g1.sA = n2;
+                    g1.B = h->d_Dt; g1.ldb = n; g1.sB = 0;
+                    g1.C = h->d_T; g1.ldc = n; g1.sC = n2;
+                    g1.nbatch = 2 * gc; g1.alpha = nullptr; g1.alpha0 = 1.0; g1.reduce = 0; g1.slices = 1;
+                    {
+                        TimedLaunch tl(h, st, 0, 2.0 * nd * nd * nd * g1.nbatch);
                         HIPCHK(launch_dgemm(g1, st));
                     }
                     for (int half = 0; half < 2; ++half) {
                         GemmArgs g2{};
-                        g2.M = g2.N = n; g2.K = rmax;
-                        g2.A = h->d_T + (long)half * gc * n * rmax; g2.lda = rmax; g2.sA = (long)n * rmax;
-                        g2.B = g2.A; g2.ldb = rmax; g2.sB = (long)n * rmax; g2.transB = 1;
+                        g2.M = g2.N = g2.K = n;
+                        g2.A = h->d_T + (long)half * gc * n2; g2.lda = n; g2.sA = n2;
+                        g2.B = h->d_F + (long)half * gc * n2; g2.ldb = n; g2.sB = n2;
                         g2.C = h->d_Kt; g2.ldc = n; g2.sC = 0;
                         g2.nbatch = gc; g2.alpha = h->d_Gw + g0; g2.alpha0 = 1.0; g2.reduce = 1; g2.upper = 1;
                         g2.slices = std::max(1, std::min(gc, 2048 / std::max(1, upper_tiles)));
-                        g2.ctl = h->d_ctl; g2.ctl_mode = 2;
-                        TimedLaunch tl(h, st, 2, nd * (nd + 1.0) * g2.nbatch);
+                        TimedLaunch tl(h, st, 0, nd * (nd + 1.0) * nd * g2.nbatch);
                         HIPCHK(launch_dgemm(g2, st));
                     }
-                }
-                // dense form: T_b = F_b D, K += W_b T_b F_b on the upper tiles (F_b symmetric)
-                GemmArgs g1{};
-                g1.M = g1.N = g1.K = n;
-                g1.A = h->d_F; g1.lda = n; g1.sA = n2;
-                g1.B = h->d_Dt; g1.ldb = n; g1.sB = 0;
-                g1.C = h->d_T; g1.ldc = n; g1.sC = n2;
-                g1.nbatch = 2 * gc; g1.alpha = nullptr; g1.alpha0 = 1.0; g1.reduce = 0; g1.slices = 1;
-                if (lowrank) { g1.ctl = h->d_ctl; g1.ctl_mode = 3; }
-                {
-                    TimedLaunch tl(h, st, lowrank ? 3 : 0, 2.0 * nd * nd * nd * g1.nbatch);
-                    HIPCHK(launch_dgemm(g1, st));
-                }
-                for (int half = 0; half < 2; ++half) {
-                    GemmArgs g2{};
-                    g2.M = g2.N = g2.K = n;
-                    g2.A = h->d_T + (long)half * gc * n2; g2.lda = n; g2.sA = n2;
-                    g2.B = h->d_F + (long)half * gc * n2; g2.ldb = n; g2.sB = n2;
-                    g2.C = h->d_Kt; g2.ldc = n; g2.sC = 0;
-                    g2.nbatch = gc; g2.alpha = h->d_Gw + g0; g2.alpha0 = 1.0; g2.reduce = 1; g2.upper = 1;
-                    g2.slices = std::max(1, std::min(gc, 2048 / std::max(1, upper_tiles)));
-                    if (lowrank) { g2.ctl = h->d_ctl; g2.ctl_mode = 3; }
-                    TimedLaunch tl(h, st, lowrank ? 3 : 0, nd * (nd + 1.0) * nd * g2.nbatch);
-                    HIPCHK(launch_dgemm(g2, st));
                 }
             }
         }
@@ -864,14 +903,16 @@ int pbc_jk_stats(const pbc_jk *hc, pbc_jk_counters *out)
         h->st.terms_fp32 = (double)cnt[23];
         for (int k = 0; k < 21; ++k) h->st.terms_class[k] = (double)cnt[2 + k];
         int ctl[4] = {0, 1, 0, 0};
-        if (h->lr_ran) HIPCHK(hipMemcpy(ctl, h->d_ctl, sizeof ctl, hipMemcpyDeviceToHost));
+        if (h->lr_ran) std::memcpy(ctl, h->h_ctl, sizeof ctl);
         const bool dense = !h->lr_ran || ctl[1];
         h->st.lr_rank = dense ? -1.0 : (double)ctl[0];
-        // the GEMM figures describe the instantiation that did the exchange
-        const int main_kind = !h->lr_ran ? 0 : dense ? 3 : 2;
-        h->st.gemm_kernel = main_kind == 0 ? 0 : main_kind == 2 ? 1 : 2;
+        // the GEMM figures describe the kernel that accumulated the exchange:
+        // k_dgemm<1> (low rank) or k_dgemm<0> (dense form, with the self term)
+        const int main_kind = dense ? 0 : 2;
+        h->st.gemm_kernel = dense ? 0 : 1;
         h->st.t_gemm_ms = h->st.t_sfac_ms = h->st.gemm_flops = h->st.t_chol_ms = 0.0;
-        h->st.n_gemm = 0;
+        h->st.t_blas_ms = h->st.blas_flops = 0.0;
+        h->st.n_gemm = h->st.n_blas = 0;
         for (int k = 0; k < 21; ++k) h->st.t_sr_class_ms[k] = 0.0;
         for (int i = 0; i < h->ntimed; ++i) {
             float ms = 0;
@@ -879,13 +920,17 @@ int pbc_jk_stats(const pbc_jk *hc, pbc_jk_counters *out)
             const int kind = h->tkind[i];
             if (kind == main_kind) {
                 h->st.t_gemm_ms += ms;
-                h->st.gemm_flops += h->tflops[i] * (kind == 2 ? (double)ctl[0] : 1.0);
+                h->st.gemm_flops += h->tflops[i];
                 h->st.n_gemm++;
+            } else if (kind == 30) {
+                h->st.t_blas_ms += ms;
+                h->st.blas_flops += h->tflops[i];
+                h->st.n_blas++;
             } else if (kind == 1) {
                 h->st.t_sfac_ms += ms;
             } else if (kind == 4) {
                 h->st.t_chol_ms += ms;
-            } else if (kind >= 5) {
+            } else if (kind >= 5 && kind < 26) {
                 h->st.t_sr_class_ms[kind - 5] += ms;
             }
         }

@@ -116,6 +116,7 @@ struct GemmArgs {
     // 3 skip unless use_dense.
     const int *ctl;
     int ctl_mode;
+    int tag;              // with ctl_mode 0: 1 launches the k_dgemm<1> instantiation
 };
 hipError_t launch_dgemm(const GemmArgs &a, hipStream_t st);
 constexpr int kGemmTile = 128;   // output tile edge of launch_dgemm

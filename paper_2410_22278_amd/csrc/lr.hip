@@ -259,8 +259,8 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs a)
 constexpr int GBM = 128, GBN = 128, GBK = 16, GPAD = 2;
 
 // GATE (separate instantiations, so that profiles tell the roles apart):
-// 0 plain, 1 low-rank exchange (ctl modes 1, 2), 2 dense exchange gated on
-// the factor being rejected (ctl mode 3).
+// 0 plain (self term, dense exchange), 1 low-rank exchange accumulation and
+// its residual check.
 template <int GATE>
 __global__ __launch_bounds__(256) void k_dgemm(GemmArgs g)
 {
@@ -696,8 +696,7 @@ hipError_t launch_dgemm(const GemmArgs &a, hipStream_t st)
     if (a.M <= 0 || a.N <= 0 || a.K <= 0 || a.nbatch <= 0) return hipSuccess;
     int z = a.reduce ? a.slices : a.nbatch;
     dim3 grid((a.N + GBN - 1) / GBN, (a.M + GBM - 1) / GBM, z);
-    if (a.ctl_mode == 0) hipLaunchKernelGGL(k_dgemm<0>, grid, dim3(256), 0, st, a);
-    else if (a.ctl_mode == 3) hipLaunchKernelGGL(k_dgemm<2>, grid, dim3(256), 0, st, a);
+    if (a.ctl_mode == 0 && !a.tag) hipLaunchKernelGGL(k_dgemm<0>, grid, dim3(256), 0, st, a);
     else hipLaunchKernelGGL(k_dgemm<1>, grid, dim3(256), 0, st, a);
     return hipGetLastError();
 }

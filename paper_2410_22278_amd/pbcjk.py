@@ -60,7 +60,8 @@ class pbc_jk_counters(ctypes.Structure):
                 ("t_other_ms", c_double), ("t_gemm_ms", c_double), ("gemm_flops", c_double),
                 ("n_gemm", c_int), ("t_sfac_ms", c_double), ("terms_class", c_double * 21),
                 ("n_group_pairs", c_double), ("lr_rank", c_double), ("t_chol_ms", c_double),
-                ("gemm_kernel", c_int), ("t_sr_class_ms", c_double * 21)]
+                ("gemm_kernel", c_int), ("t_sr_class_ms", c_double * 21), ("t_blas_ms", c_double),
+                ("blas_flops", c_double), ("n_blas", c_int)]
 
 
 class pbc_jk_server_config(ctypes.Structure):
