@@ -85,6 +85,9 @@ WORKLOADS = {
             "nbf 832, omega 0.3, delta 1e-10, D = C C^T (832x320), FP64",
     "cfg3": "the 64-water cell of cfg2 in mixed precision: FP32 short-range quartets below a "
             "density-weighted bound of 1e-6, FP64 accumulation and reciprocal sum",
+    "cfg4": "diamond 4x4x4 supercell (512 atoms, a=21.72 A, N(0, 0.05 A) displacements), 2s+2p+1d (spherical) "
+            "per atom, 3 prims in [0.08, 10], nbf 6656, omega 0.2, delta 1e-11, D = C C^T (6656x1024), FP64",
+    "cfg4m": "the diamond cell of cfg4 in mixed precision (FP32 short-range quartets below 1e-6)",
     "cfg5": "serving stream: cubic H/C/O cells of 8-216 atoms (log-uniform) at 0.1 atoms/A^3, mixed precision, "
             "D = C C^T with nbf/4 orbitals, Poisson arrivals at 0.8x the measured saturated rate, through the "
             "library's request server (4 slots, HBM arena admission)",
@@ -100,6 +103,8 @@ def cpu_baseline(system, name):
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     if name == "cfg3":
         name = "cfg2"    # the oracle is FP64 only: same workload
+    if name in ("cfg4", "cfg4m"):
+        return None      # the oracle needs ~20 min for three bra shells of this cell
     if name == "cfg1":
         t0 = time.perf_counter()
         oracle.jk(system)
