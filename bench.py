@@ -300,8 +300,13 @@ def main():
         cb, ck = SLOTS[k]
         la, lb = CLASSES[cb]
         lc, ld = CLASSES[ck]
-        coop = (cb, ck) in COOP_SLOTS
-        name = (f"k_sr_coop<{la}, {lb}, {lc}, {ld}>" if coop else f"k_sr_jk<{la}, {lb}, {lc}, {ld}, ...>")
+        fold = "true" if (st["sr_fold_mask"] >> k) & 1 else "false"
+        if (st["sr_kernel_mask"] >> k) & 1:
+            name = f"k_sr_coop<{la}, {lb}, {lc}, {ld}> (or k_sr_coop2)"
+        elif (cb, ck) in COOP_SLOTS:
+            name = f"k_sr_jk<{la}, {lb}, {lc}, {ld}, double, {fold}, *> (component slices)"
+        else:
+            name = f"k_sr_jk<{la}, {lb}, {lc}, {ld}, double, {fold}, 0, {_nc(lc)}>"
         cands.append({
             "kernel": f"{name}: short-range J/K, class pair ({CLASS_NAMES[cb]}|{CLASS_NAMES[ck]})", "name": name,
             "bound": "alu", "ms_per_build": t, "flops_per_build": sr_terms_class[k] / steps * sr_flops_per_term(cb, ck),

@@ -144,6 +144,11 @@ typedef struct {
     double t_blas_ms;    /* last build: duration of the rocBLAS products Y = F L (low rank)    */
     double blas_flops;   /* last build: their FLOPs (2 n^2 rank per F matrix)                  */
     int n_blas;          /* last build: number of those rocBLAS calls                          */
+    int sr_fold_mask;    /* last build: bit k set when class pair k summed its lattice shifts
+                            before the transforms                                              */
+    int sr_kernel_mask;  /* last build: bit k set when class pair k ran one wavefront per group
+                            pair (else one lane per group pair, in component slices for the
+                            large d pairs)                                                     */
 } pbc_jk_counters;
 
 /* Creates a handle: validates and copies the inputs, builds the local pair

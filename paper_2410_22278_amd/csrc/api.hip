@@ -22,6 +22,9 @@ namespace {
 constexpr int kClassL[kNumClass] = {0, 1, 2, 2, 3, 4};
 constexpr int kNumCounters = 48;     // see SRArgs::counters
 
+// Large d class pairs with component-slice launches of the per-lane kernel.
+bool sr_sliceable(int cb, int ck) { return !(cb == 5 && ck == 5); }
+
 // Class pairs (cb <= ck) with a per-lane register kernel: everything without
 // a d shell, and the d pairs (ds|ss), (dp|ss), (ds|ps), (dp|ps), (ds|pp), (ds|ds).
 bool sr_per_lane(int cb, int ck)
@@ -467,6 +470,7 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
     // B3/B4: short-range J and K.  Per class pair: the density-weighted
     // screen compacts the neighbour list into FP64 and FP32 work lists, then
     // one launch per list.
+    h->st.sr_fold_mask = h->st.sr_kernel_mask = 0;
     if (h->parts & PBC_JK_PART_SR) {
         HIPCHK(launch_fill((double *)h->d_wcnt, 42, 0.0, st));
         SRArgs a{};
@@ -511,6 +515,8 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
                     a.count = !split ? h->d_ncnt + slot : h->d_wcnt + 2 * slot + prec;
                     // the FP32 list always sums its shifts in FP64 before the transforms
                     TimedLaunch tl(h, st, 5 + slot, 0.0);
+                    if (h->fold[slot]) h->st.sr_fold_mask |= 1 << slot;
+                    if (coop && (h->coop_d[slot] || !sr_sliceable(cb, ck))) h->st.sr_kernel_mask |= 1 << slot;
                     hipError_t e;
                     if (!coop) e = launch_sr_jk(cb, ck, a, prec == 1, h->fold[slot], st);
                     else if (!h->coop_d[slot]) e = launch_sr_slices(cb, ck, a, h->fold[slot], st);

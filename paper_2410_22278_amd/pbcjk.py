@@ -61,7 +61,8 @@ class pbc_jk_counters(ctypes.Structure):
                 ("n_gemm", c_int), ("t_sfac_ms", c_double), ("terms_class", c_double * 21),
                 ("n_group_pairs", c_double), ("lr_rank", c_double), ("t_chol_ms", c_double),
                 ("gemm_kernel", c_int), ("t_sr_class_ms", c_double * 21), ("t_blas_ms", c_double),
-                ("blas_flops", c_double), ("n_blas", c_int)]
+                ("blas_flops", c_double), ("n_blas", c_int), ("sr_fold_mask", c_int),
+                ("sr_kernel_mask", c_int)]
 
 
 class pbc_jk_server_config(ctypes.Structure):
