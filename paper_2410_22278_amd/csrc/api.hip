@@ -72,7 +72,7 @@ struct pbc_jk {
     // setup data
     PairRec *d_pairs = nullptr;
     GroupRec *d_groups = nullptr;
-    double *d_boys = nullptr, *d_S = nullptr, *d_G = nullptr, *d_Gw = nullptr;
+    double *d_boys = nullptr, *d_bexp = nullptr, *d_S = nullptr, *d_G = nullptr, *d_Gw = nullptr;
     int *d_sp_start = nullptr, *d_sp_pairs = nullptr, *d_sp_shA = nullptr, *d_sp_shB = nullptr;
     int *d_sh_l = nullptr, *d_sh_aoc = nullptr, *d_tr_ao = nullptr, *d_inv_ci = nullptr;
     double *d_tr_c = nullptr, *d_dscale = nullptr, *d_inv_cc = nullptr;
@@ -170,7 +170,7 @@ int upload(pbc_jk *h, T **p, const std::vector<T> &v)
 // setup are kept, so the device part can be created again).
 void release_device(pbc_jk *h)
 {
-    void **pp[] = {(void **)&h->d_pairs, (void **)&h->d_groups, (void **)&h->d_boys, (void **)&h->d_S,
+    void **pp[] = {(void **)&h->d_pairs, (void **)&h->d_groups, (void **)&h->d_boys, (void **)&h->d_bexp, (void **)&h->d_S,
                    (void **)&h->d_G, (void **)&h->d_Gw, (void **)&h->d_sp_start, (void **)&h->d_sp_pairs,
                    (void **)&h->d_sp_shA, (void **)&h->d_sp_shB, (void **)&h->d_sh_l, (void **)&h->d_sh_aoc,
                    (void **)&h->d_tr_ao, (void **)&h->d_inv_ci, (void **)&h->d_tr_c, (void **)&h->d_dscale,
@@ -249,6 +249,7 @@ int create_device(pbc_jk *h)
     if ((rc = upload(h, &h->d_pairs, S.pairs))) return rc;
     if ((rc = upload(h, &h->d_groups, S.groups))) return rc;
     if ((rc = upload(h, &h->d_boys, S.boys))) return rc;
+    if ((rc = upload(h, &h->d_bexp, S.bexp))) return rc;
     if ((rc = upload(h, &h->d_S, S.S))) return rc;
     if ((rc = upload(h, &h->d_G, S.G))) return rc;
     if ((rc = upload(h, &h->d_Gw, S.Gw))) return rc;
@@ -481,7 +482,7 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
         a.w2 = S.omega * S.omega; a.d_schwarz = S.d_schwarz; a.d_ewald_R = S.d_ewald_R;
         a.rcap2 = S.r_cut > 0 ? S.r_cut * S.r_cut : 0.0;
         a.fp32_below = S.fp32_below;
-        a.boys = h->d_boys; a.counters = h->d_cnt;
+        a.boys = h->d_boys; a.bexp = h->d_bexp; a.counters = h->d_cnt;
         int slot = 0;
         for (int cb = 0; cb < kNumClass; ++cb)
             for (int ck = cb; ck < kNumClass; ++ck, ++slot) {
@@ -543,7 +544,7 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
         if (lowrank) {
             // D~ = L L^T on the device; R = L L^T into T, then the entrywise check
             TimedLaunch tl(h, st, 4, 0.0);
-            HIPCHK(launch_pchol(h->d_Dt, n, h->lr_tol, rmax, h->d_L, h->d_pw, h->d_pwi, h->d_ctl, st));
+            HIPCHK(launch_pchol(h->d_Dt, n, h->lr_tol, rmax, h->d_L, h->d_pw, h->d_pwi, h->d_ctl, h->h_ctl, st));
             GemmArgs gr{};
             gr.M = gr.N = n; gr.K = rmax;
             gr.A = h->d_L; gr.lda = n; gr.sA = 0; gr.transA = 1;

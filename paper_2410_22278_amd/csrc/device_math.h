@@ -84,30 +84,66 @@ __device__ __forceinline__ void herm_R(const V (&R0)[L + 1], V X, V Y, V Z, V (&
             for (int v = 0; v <= L - t - u; ++v) R[t][u][v] = T[0][t][u][v];
 }
 
+// FP64 reciprocal and reciprocal square root: the hardware approximation
+// refined by two Newton steps (correct to about one unit in the last place,
+// which is all the kernels need; no IEEE-rounded division sequence).
+__device__ __forceinline__ double fast_rcp(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+__device__ __forceinline__ double fast_rsqrt(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    // y <- y (3 - x y^2) / 2, twice
+    double h = 0.5 * x;
+    y = y * fma(-h * y, y, 1.5);
+    return y * fma(-h * y, y, 1.5);
+}
+
 // F_m(T), m = 0..L, FP64.  tab: LDS copy of rows L..L+kBoysTerms-1,
 // layout [k][j].  Below kBoysTmax: Taylor expansion of F_L about the
 // nearest grid point, then downward recursion; above: asymptotic F_0 and
 // upward recursion.
-template <int L, int STRIDE = kBoysTerms>
-__device__ __forceinline__ void boys_f64(double T, const double *__restrict__ tab, double (&F)[L + 1])
+// PREDIV: the table row holds F_{L+j}(T_k) / j! (the per-lane kernels
+// divide while copying the table to LDS), so Horner needs one FMA a term.
+template <int L, int STRIDE = kBoysTerms, bool PREDIV = false>
+__device__ __forceinline__ void boys_f64(double T, const double *__restrict__ tab, const double *__restrict__ etab,
+                                         double (&F)[L + 1])
 {
     if (T < kBoysTmax) {
         int k = __double2int_rn(T * (1.0 / kBoysStep));
         double x = k * kBoysStep - T;
         const double *r = tab + k * STRIDE;
         double s = r[kBoysTerms - 1];
+        if (PREDIV) {
 #pragma unroll
-        for (int j = kBoysTerms - 2; j >= 0; --j) s = r[j] + s * x * (1.0 / (j + 1));
+            for (int j = kBoysTerms - 2; j >= 0; --j) s = fma(s, x, r[j]);
+        } else {
+#pragma unroll
+            for (int j = kBoysTerms - 2; j >= 0; --j) s = r[j] + s * x * (1.0 / (j + 1));
+        }
         F[L] = s;
         if (L > 0) {
-            double e = exp(-T);
+            // e^{-T} = e^{-T_k} e^{x}, |x| <= h/2: e^{x} by its Taylor series
+            constexpr double c[9] = {1.0, 1.0, 1.0 / 2, 1.0 / 6, 1.0 / 24, 1.0 / 120, 1.0 / 720, 1.0 / 5040,
+                                     1.0 / 40320};
+            double ex = c[8];
+#pragma unroll
+            for (int j = 7; j >= 0; --j) ex = fma(ex, x, c[j]);
+            const double e = etab[k] * ex;
 #pragma unroll
             for (int m = L - 1; m >= 0; --m) F[m] = (2.0 * T * F[m + 1] + e) * (1.0 / (2 * m + 1));
         }
     } else {
-        double it = 1.0 / T;
-        F[0] = 0.88622692545275801365 * sqrt(it);   // sqrt(pi)/2 / sqrt(T)
+        const double rs = fast_rsqrt(T);
+        F[0] = 0.88622692545275801365 * rs;   // sqrt(pi)/2 / sqrt(T)
         if (L > 0) {
+            const double it = rs * rs;
             double e = exp(-T);
 #pragma unroll
             for (int m = 0; m < L; ++m) F[m + 1] = ((2 * m + 1) * F[m] - e) * (0.5 * it);
@@ -119,16 +155,17 @@ __device__ __forceinline__ void boys_f64(double T, const double *__restrict__ ta
 // T = |L|^2 (Sec. 2.3 Boys split):
 //   (-2 rho)^m F_m(rho T) - c (-2 a')^m F_m(a' T),
 //   a' = rho w^2/(rho + w^2), c = w/sqrt(rho + w^2).
-template <int L, int STRIDE = kBoysTerms>
+template <int L, int STRIDE = kBoysTerms, bool PREDIV = false>
 __device__ __forceinline__ void sr_R0(double rho, double w2, double T, const double *__restrict__ tab,
-                                      double (&R0)[L + 1])
+                                      const double *__restrict__ etab, double (&R0)[L + 1])
 {
-    double den = 1.0 / (rho + w2);
-    double ap = rho * w2 * den;
-    double c = sqrt(w2 * den);
+    const double rs = fast_rsqrt(rho + w2);
+    const double den = rs * rs;
+    const double ap = rho * w2 * den;
+    const double c = sqrt(w2) * rs;
     double F1[L + 1], F2[L + 1];
-    boys_f64<L, STRIDE>(rho * T, tab, F1);
-    boys_f64<L, STRIDE>(ap * T, tab, F2);
+    boys_f64<L, STRIDE, PREDIV>(rho * T, tab, etab, F1);
+    boys_f64<L, STRIDE, PREDIV>(ap * T, tab, etab, F2);
     double f1 = 1.0, f2 = c;
 #pragma unroll
     for (int m = 0; m <= L; ++m) {
@@ -138,8 +175,9 @@ __device__ __forceinline__ void sr_R0(double rho, double w2, double T, const dou
     }
 }
 
-// FP32 F_m(T) from the same table (six Taylor terms suffice in single
-// precision); the offset from the grid point is formed in FP64.
+// FP32 F_m(T) from the same table, pre-divided by j! as for PREDIV (six
+// Taylor terms suffice in single precision); the offset from the grid point
+// is formed in FP64.
 template <int L>
 __device__ __forceinline__ void boys_f32(double Td, const double *__restrict__ tab, float (&F)[L + 1])
 {
@@ -147,10 +185,10 @@ __device__ __forceinline__ void boys_f32(double Td, const double *__restrict__ t
     if (Td < kBoysTmax) {
         int k = __double2int_rn(Td * (1.0 / kBoysStep));
         float x = (float)(k * kBoysStep - Td);
-        const double *r = tab + k * kBoysTerms;
+        const double *r = tab + k * kBoysTerms;   // F_{L+j}(T_k) / j!
         float s = (float)r[5];
 #pragma unroll
-        for (int j = 4; j >= 0; --j) s = (float)r[j] + s * x * (1.0f / (j + 1));
+        for (int j = 4; j >= 0; --j) s = fmaf(s, x, (float)r[j]);
         F[L] = s;
         if (L > 0) {
             float e = __expf(-T);
@@ -173,11 +211,11 @@ __device__ __forceinline__ void boys_f32(double Td, const double *__restrict__ t
 // difference 1 - c ... cancels) are evaluated in FP64 and rounded.
 template <int L>
 __device__ __forceinline__ void sr_R0_mixed(double rho, double w2, double T, const double *__restrict__ tab,
-                                            float (&R0)[L + 1])
+                                            const double *__restrict__ etab, float (&R0)[L + 1])
 {
     if (rho * T < 1.0) {
         double R0d[L + 1];
-        sr_R0<L>(rho, w2, T, tab, R0d);
+        sr_R0<L, kBoysTerms, true>(rho, w2, T, tab, etab, R0d);
 #pragma unroll
         for (int m = 0; m <= L; ++m) R0[m] = (float)R0d[m];
         return;
@@ -207,13 +245,14 @@ constexpr double kTwoPi52 = 34.98683665524972497;   // 2 pi^{5/2}
 __device__ __forceinline__ bool quartet_sphere(const PairRec &b, const PairRec &k, double w2, double dR,
                                                double &rad2)
 {
-    const double p = b.p, q = k.p, pq = p * q;
-    const double rho = pq / (p + q);
-    const double c = sqrt(w2 / (rho + w2));
-    const double C2e = b.Cb * k.Cb * kTwoPi52 / (pq * sqrt(p + q));
-    const double arg = C2e * (1.0 - c) / dR;
+    const double p = b.p, q = k.p;
+    const double ip = b.pad[0], iq = k.pad[0];          // 1/p, 1/q
+    const double rho = fast_rcp(ip + iq);
+    const double c = sqrt(w2) * fast_rsqrt(rho + w2);
+    const double C2e = b.Cb * k.Cb * kTwoPi52 * ip * iq * fast_rsqrt(p + q);
+    const double arg = C2e * (1.0 - c) * fast_rcp(dR);
     if (!(arg > 1.0)) return false;
-    rad2 = (1.0 / p + 1.0 / q + 1.0 / w2) * log(arg);
+    rad2 = (ip + iq + fast_rcp(w2)) * log(arg);
     return true;
 }
 
@@ -231,14 +270,17 @@ template <class F>
 __device__ __forceinline__ void for_images(const LatArgs &lat, const double cen[3], double rad2, double rcap2,
                                            F &&f)
 {
+    if (!(rad2 > 0.0)) return;   // empty sphere (also keeps the box below finite)
     double fr[3];
 #pragma unroll
     for (int x = 0; x < 3; ++x) fr[x] = cen[0] * lat.Minv[x] + cen[1] * lat.Minv[3 + x] + cen[2] * lat.Minv[6 + x];
     double L[3];
     lat_image(lat, cen, (int)rint(fr[0]), (int)rint(fr[1]), (int)rint(fr[2]), L);
     const double L2 = L[0] * L[0] + L[1] * L[1] + L[2] * L[2];
-    const double rad = sqrt(rad2);
-    if (rad <= lat.Rmin - sqrt(L2)) {
+    const double rad = rad2 * fast_rsqrt(rad2);
+    const double gap = lat.Rmin - rad;
+    // |L0| <= Rmin - rad: no other translate can lie inside the sphere
+    if (gap >= 0.0 && L2 <= gap * gap) {
         if (L2 < rad2 && !(rcap2 > 0 && L2 > rcap2)) f(L, L2);
         return;
     }

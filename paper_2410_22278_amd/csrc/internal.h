@@ -33,7 +33,7 @@ struct alignas(32) PairRec {
     double PB[3];   // P - B(image)
     double Q;       // local-pair Cauchy-Schwarz value 2^{1/4} pi^{5/4} |Ca Cb| K / p^{5/4}
     double Cb;      // |Ca Cb| K without the symmetry weight (real-space sphere bound)
-    double pad[3];
+    double pad[3];   // pad[0] = 1/p
 };
 
 // A group: one (first shell, second shell, image) with its primitive pairs.
@@ -85,6 +85,7 @@ struct Setup {
     std::vector<double> Gw;         // 2 w_G (both signs folded)
     std::vector<double> S;          // scaled-Cartesian Gamma overlap, nbfc^2
     std::vector<double> boys;       // kBoysNT * kBoysM
+    std::vector<double> bexp;       // kBoysNT: e^{-k h}
     std::vector<int> sp_start;      // unique shell pairs: ranges into sp_pairs
     std::vector<int> sp_pairs;      // pair indices grouped by shell pair
     std::vector<int> sp_shA, sp_shB;

@@ -25,6 +25,7 @@ struct SRArgs {
     double w2, d_schwarz, d_ewald_R, rcap2;
     double fp32_below;    // > 0: quartets with Q Q w_D below it are evaluated in FP32
     const double *boys;   // kBoysNT x kBoysM
+    const double *bexp;   // kBoysNT: e^{-k h} on the Boys grid
     unsigned long long *counters;   // [0] primitive quartets, [1] (quartet, R1) terms,
                                     // [2 + slot] terms of this class pair, [23] FP32 terms,
                                     // [24 + slot] primitive quartets of this class pair
@@ -129,7 +130,7 @@ constexpr int kGemmTile = 128;   // output tile edge of launch_dgemm
 // 2 * ceil(n / 64) ints (wi).  use_dense is set when the factor did not
 // converge within rmax columns or D has a diagonal entry below -tol * max.
 hipError_t launch_pchol(const double *D, int n, double tol, int rmax, double *L, double *work, int *wi,
-                        int *ctl, hipStream_t st);
+                        int *ctl, int *h_ctl, hipStream_t st);   // h_ctl: pinned host copy (4 ints)
 // After R = L L^T: sets ctl[1] when max |D - R| exceeds 2 tol max diag(D)
 // plus the rounding allowance 4 n eps max diag(D).
 hipError_t launch_lowrank_check(const double *D, const double *R, int n, const double *work, int *ctl,

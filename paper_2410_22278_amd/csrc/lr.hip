@@ -34,7 +34,7 @@ __device__ __forceinline__ void sfac_pairs(const SfacArgs &a, int sp, double Gx,
         for (int j = 0; j < NB; ++j) { re[i][j] = 0.0; im[i][j] = 0.0; }
     for (int k = a.sp_start[sp]; k < a.sp_start[sp + 1]; ++k) {
         const PairRec P = a.pairs[a.sp_pairs[k]];
-        const double ip = 1.0 / P.p;
+        const double ip = P.pad[0];   // 1/p
         const double pre = P.cpre * exp(-0.25 * G2 * ip) * (kPi * ip) * sqrt(kPi * ip);
         double s, c;
         sincos(Gx * P.P[0] + Gy * P.P[1] + Gz * P.P[2], &s, &c);
@@ -638,7 +638,7 @@ __global__ __launch_bounds__(256) void k_lowrank_check(const double *D, const do
 }  // namespace
 
 hipError_t launch_pchol(const double *D, int n, double tol, int rmax, double *L, double *work, int *wi,
-                        int *ctl, hipStream_t st)
+                        int *ctl, int *h_ctl, hipStream_t st)
 {
     const int nblk = (n + kCholRows - 1) / kCholRows;
     if (n <= kCholSingleMax) {
@@ -646,8 +646,20 @@ hipError_t launch_pchol(const double *D, int n, double tol, int rmax, double *L,
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_pchol_init, dim3(1), dim3(1024), 0, st, D, n, tol, work, wi, ctl);
-    for (int k = 0; k < rmax; ++k)
-        hipLaunchKernelGGL(k_pchol_step, dim3(nblk), dim3(256), 0, st, D, n, k, L, work, wi, ctl);
+    // columns in chunks; between chunks the host reads the stop flag, so
+    // that no launches are queued far beyond the rank
+    constexpr int kChunk = 64;
+    for (int k0 = 0; k0 < rmax; k0 += kChunk) {
+        const int k1 = std::min(rmax, k0 + kChunk);
+        for (int k = k0; k < k1; ++k)
+            hipLaunchKernelGGL(k_pchol_step, dim3(nblk), dim3(256), 0, st, D, n, k, L, work, wi, ctl);
+        if (k1 < rmax) {
+            hipError_t e = hipMemcpyAsync(h_ctl, ctl, 4 * sizeof(int), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) return e;
+            if (h_ctl[2]) break;
+        }
+    }
     hipLaunchKernelGGL(k_pchol_fin, dim3(1), dim3(256), 0, st, n, rmax, (const double *)work, (const int *)wi, ctl);
     return hipGetLastError();
 }

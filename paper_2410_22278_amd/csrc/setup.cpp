@@ -129,6 +129,13 @@ double boys_host(int m, double T)
     return (double)(std::exp(-(long double)T) * sum);
 }
 
+// e^{-T_k} on the Boys grid (the kernels form e^{-T} from it)
+void boys_exp_table(std::vector<double> &etab)
+{
+    etab.resize(kBoysNT);
+    for (int k = 0; k < kBoysNT; ++k) etab[k] = (double)std::exp(-(long double)(k * (long double)kBoysStep));
+}
+
 void boys_table(std::vector<double> &tab)
 {
     tab.assign((size_t)kBoysNT * kBoysM, 0.0);
@@ -303,7 +310,8 @@ int build_setup(const double *cell, int natom, const double *xyz, int nshell, co
                         t.rec.cpre = ca * cb * nbase(a, la) * nbase(b, lb) * g * fw;
                         t.rec.Q = Y0 * g;
                         t.rec.Cb = Cab * g;
-                        t.rec.pad[0] = t.rec.pad[1] = t.rec.pad[2] = 0.0;
+                        t.rec.pad[0] = 1.0 / p;
+                        t.rec.pad[1] = t.rec.pad[2] = 0.0;
                         // Separable real-space bound: C2e (1 - c) <= Z_bra Z_ket, using
                         // 2pi^{5/2}/(pq sqrt(p+q)) <= prod sqrt2 pi^{5/4}/(p (p+2amin)^{1/4})
                         // and 1 - w/sqrt(rho+w^2) <= sqrt(prod (1 - w/sqrt(p+w^2))).
@@ -456,6 +464,7 @@ int build_setup(const double *cell, int natom, const double *xyz, int nshell, co
                 S.S[(size_t)i * S.nbfc + j] = Sh[(size_t)i * S.nbfc + j] + Sh[(size_t)j * S.nbfc + i];
     }
     boys_table(S.boys);
+    boys_exp_table(S.bexp);
     return 0;
 }
 

@@ -118,7 +118,7 @@ __global__ __launch_bounds__(64) void k_sr_coop(SRArgs a)
             for_images(a.lat, cen, rad2, a.rcap2, [&](const double *Lv, double L2) {
                 ++nimg;
                 double R0[L + 1];
-                sr_R0<L, kBoysM>(rho, a.w2, L2, tab, R0);
+                sr_R0<L, kBoysM>(rho, a.w2, L2, tab, a.bexp, R0);
                 // R recurrence, one level at a time: level n holds t+u+v <= L-n
                 int cur = 0;
                 if (lane == 0) sR[0][0] = R0[L];
@@ -397,7 +397,7 @@ __global__ __launch_bounds__(64) void k_sr_coop2(SRArgs a)
                     for_images(a.lat, cen, rad2, a.rcap2, [&](const double *Lv, double L2) {
                         ++nimg;
                         double R0[L + 1];
-                        sr_R0<L, kBoysM>(rho, a.w2, L2, tab, R0);
+                        sr_R0<L, kBoysM>(rho, a.w2, L2, tab, a.bexp, R0);
                         double R[L + 1][L + 1][L + 1];
                         herm_R<L, double>(R0, Lv[0], Lv[1], Lv[2], R);
 #pragma unroll

@@ -153,18 +153,29 @@ __device__ __forceinline__ void scatter_block(const SRArgs &a, const double (&ac
 // class pairs run one launch per slice so that the slice fits in registers,
 // each recomputing the shifts' Hermite integrals).  Counters are kept by the
 // slice that starts at component 0.
+// Class pairs with small blocks keep three wavefronts per SIMD (their
+// register use sits just above the two-wavefront line otherwise).
+template <int LA, int LB, int LC, int LD>
+constexpr int sr_waves_per_eu() { return (LA + LB + LC + LD <= 1) ? 3 : 1; }
+
 template <int LA, int LB, int LC, int LD, typename V, bool FOLD, int IC0 = 0, int NIC = ncart(LC)>
-__global__ __launch_bounds__(256) void k_sr_jk(SRArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sr_waves_per_eu<LA, LB, LC, LD>())))
+void k_sr_jk(SRArgs a)
 {
     constexpr int L = LA + LB + LC + LD;
     constexpr int NA = ncart(LA), NB = ncart(LB), ND = ncart(LD);
     constexpr bool COUNT = IC0 == 0;
     constexpr bool F32 = sizeof(V) == 4;
     __shared__ double tab[kBoysNT * kBoysTerms];
+    __shared__ double etab[kBoysNT];
+    // Taylor coefficients F_{L+j}(T_k) / j!
+    constexpr double kInvFact[kBoysTerms] = {1.0, 1.0, 1.0 / 2, 1.0 / 6, 1.0 / 24, 1.0 / 120, 1.0 / 720,
+                                             1.0 / 5040, 1.0 / 40320};
     for (int i = threadIdx.x; i < kBoysNT * kBoysTerms; i += blockDim.x) {
         int k = i / kBoysTerms, j = i - k * kBoysTerms;
-        tab[i] = a.boys[k * kBoysM + L + j];
+        tab[i] = a.boys[k * kBoysM + L + j] * kInvFact[j];
     }
+    for (int i = threadIdx.x; i < kBoysNT; i += blockDim.x) etab[i] = a.bexp[i];
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int ns = a.nshell;
@@ -201,7 +212,7 @@ __global__ __launch_bounds__(256) void k_sr_jk(SRArgs a)
         for (int pk = gk.pstart; pk < pk_end; ++pk) {
             const PairRec Pk = a.pairs[pk];
             EAxis<LC, LD> Fx, Fy, Fz;
-            const double hk = 0.5 / Pk.p;
+            const double hk = 0.5 * Pk.pad[0];
             herm_axis<LC, LD>(hk, Pk.PA[0], Pk.PB[0], Fx);
             herm_axis<LC, LD>(hk, Pk.PA[1], Pk.PB[1], Fy);
             herm_axis<LC, LD>(hk, Pk.PA[2], Pk.PB[2], Fz);
@@ -211,11 +222,11 @@ __global__ __launch_bounds__(256) void k_sr_jk(SRArgs a)
                 ++cnt_q;
                 double rad2;
                 if (!quartet_sphere(Pb, Pk, a.w2, a.d_ewald_R, rad2)) continue;
-                const double p = Pb.p, q = Pk.p, pq = p * q;
-                const double rho = pq / (p + q);
-                const double pref = Pb.cpre * Pk.cpre * kTwoPi52 / (pq * sqrt(p + q));
+                const double p = Pb.p, q = Pk.p;
+                const double rho = fast_rcp(Pb.pad[0] + Pk.pad[0]);
+                const double pref = Pb.cpre * Pk.cpre * kTwoPi52 * Pb.pad[0] * Pk.pad[0] * fast_rsqrt(p + q);
                 EAxis<LA, LB> Ex, Ey, Ez;
-                const double hb = 0.5 / p;
+                const double hb = 0.5 * Pb.pad[0];
                 herm_axis<LA, LB>(hb, Pb.PA[0], Pb.PB[0], Ex);
                 herm_axis<LA, LB>(hb, Pb.PA[1], Pb.PB[1], Ey);
                 herm_axis<LA, LB>(hb, Pb.PA[2], Pb.PB[2], Ez);
@@ -234,7 +245,7 @@ __global__ __launch_bounds__(256) void k_sr_jk(SRArgs a)
                         ++nimg;
                         if (F32) {
                             float R0[L + 1];
-                            sr_R0_mixed<L>(rho, a.w2, L2, tab, R0);
+                            sr_R0_mixed<L>(rho, a.w2, L2, tab, etab, R0);
                             float R[L + 1][L + 1][L + 1];
                             herm_R<L, float>(R0, (float)Lv[0], (float)Lv[1], (float)Lv[2], R);
 #pragma unroll
@@ -245,7 +256,7 @@ __global__ __launch_bounds__(256) void k_sr_jk(SRArgs a)
                                     for (int v = 0; v <= L - t - u; ++v) Rs[t][u][v] += (double)R[t][u][v];
                         } else {
                             double R0[L + 1];
-                            sr_R0<L>(rho, a.w2, L2, tab, R0);
+                            sr_R0<L, kBoysTerms, true>(rho, a.w2, L2, tab, etab, R0);
                             double R[L + 1][L + 1][L + 1];
                             herm_R<L, double>(R0, Lv[0], Lv[1], Lv[2], R);
 #pragma unroll
@@ -273,13 +284,13 @@ __global__ __launch_bounds__(256) void k_sr_jk(SRArgs a)
                         ++ent_terms;
                         if (F32) {
                             float R0[L + 1];
-                            sr_R0_mixed<L>(rho, a.w2, L2, tab, R0);
+                            sr_R0_mixed<L>(rho, a.w2, L2, tab, etab, R0);
                             float R[L + 1][L + 1][L + 1];
                             herm_R<L, float>(R0, (float)Lv[0], (float)Lv[1], (float)Lv[2], R);
                             add_term<LA, LB, LC, LD, float, IC0, NIC>(Ex, Ey, Ez, Fx, Fy, Fz, R, pref, acc);
                         } else {
                             double R0[L + 1];
-                            sr_R0<L>(rho, a.w2, L2, tab, R0);
+                            sr_R0<L, kBoysTerms, true>(rho, a.w2, L2, tab, etab, R0);
                             double R[L + 1][L + 1][L + 1];
                             herm_R<L, double>(R0, Lv[0], Lv[1], Lv[2], R);
                             add_term<LA, LB, LC, LD, double, IC0, NIC>(Ex, Ey, Ez, Fx, Fy, Fz, R, pref, acc);
