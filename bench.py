@@ -279,9 +279,10 @@ def main():
     steps = args.steps
     # GEMM instantiation that formed the reciprocal exchange
     gk = st["gemm_kernel"]
-    gemm_name = f"k_dgemm<{gk}>"
+    gemm_name = "rocblas_dgemm_strided_batched (Y Y^T)" if gk == 2 else f"k_dgemm<{gk}>"
     gemm_role = {0: "dense exchange T_G = F_G D, K += W_G T_G F_G, and the self term",
-                 1: "low-rank exchange accumulation K += W_G Y_G Y_G^T (D = L L^T) and the factor's residual check"}[gk]
+                 2: "low-rank exchange accumulation K += sum_G Y_G Y_G^T in chunks (D = L L^T, "
+                    "FLOPs counted on the upper triangle)"}[gk]
     cands = [{
         "kernel": f"{gemm_name}: {gemm_role}", "name": gemm_name, "bound": "mfma",
         "ms_per_build": gemm_ms / steps, "flops_per_build": gemm_fl / steps,
@@ -289,7 +290,7 @@ def main():
     }]
     if blas_ms > 0:
         cands.append({
-            "kernel": "rocBLAS dgemm_strided_batched: Y_G = F_G L", "name": "rocblas_dgemm_strided_batched",
+            "kernel": "rocBLAS dgemm_strided_batched: Y_G = F_G L", "name": "rocblas_dgemm_strided_batched (F L)",
             "bound": "mfma", "ms_per_build": blas_ms / steps, "flops_per_build": blas_fl / steps,
             "launches_per_build": n_blas / steps, "peak": FP64_MFMA_PEAK_TFLOPS,
         })

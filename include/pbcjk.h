@@ -135,10 +135,12 @@ typedef struct {
                                have a term for some density)                            */
     double lr_rank;      /* last build: rank of the density factor used by the reciprocal
                             exchange, or -1 when the dense form was used                */
-    double t_chol_ms;    /* last build: duration of the density factorisation               */
-    int gemm_kernel;     /* instantiation of t_gemm_ms: 0 k_dgemm<0> (dense exchange and self
-                            term), 1 k_dgemm<1> (low-rank accumulation K += W Y Y^T and the
-                            residual check of the factor)                                      */
+    double t_chol_ms;    /* last build: duration of the density factorisation and of its
+                            residual check                                                     */
+    int gemm_kernel;     /* kernel of t_gemm_ms: 0 k_dgemm<0> (dense exchange and self term),
+                            2 rocBLAS strided-batched products of the low-rank accumulation
+                            K += sum_G Y_G Y_G^T (Y_G = sqrt(W_G) F_G L), FLOPs counted on the
+                            upper triangle; 1 is no longer produced                            */
     double t_sr_class_ms[21]; /* last build: duration of the short-range launches per class
                             pair (same order as terms_class)                                   */
     double t_blas_ms;    /* last build: duration of the rocBLAS products Y = F L (low rank)    */

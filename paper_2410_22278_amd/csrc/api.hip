@@ -36,6 +36,7 @@ bool sr_per_lane(int cb, int ck)
 }
 constexpr double kFoldRmin = 20.0;   // bohr: cells with a shorter lattice vector start folded
 constexpr double kFoldRatio = 1.1;   // shifts per quartet above which the lattice sum is folded
+constexpr long kStage2Tiles = 8192;  // 128 x 128 output tiles aimed at by the split exchange reduction
 constexpr double kCoopRatio = 4.5;   // shifts per quartet above which large d pairs use one
                                      // wavefront per group pair (it evaluates each shift once)
 
@@ -72,7 +73,7 @@ struct pbc_jk {
     // setup data
     PairRec *d_pairs = nullptr;
     GroupRec *d_groups = nullptr;
-    double *d_boys = nullptr, *d_bexp = nullptr, *d_S = nullptr, *d_G = nullptr, *d_Gw = nullptr;
+    double *d_boys = nullptr, *d_bexp = nullptr, *d_S = nullptr, *d_G = nullptr, *d_Gw = nullptr, *d_Gs = nullptr;
     int *d_sp_start = nullptr, *d_sp_pairs = nullptr, *d_sp_shA = nullptr, *d_sp_shB = nullptr;
     int *d_sh_l = nullptr, *d_sh_aoc = nullptr, *d_tr_ao = nullptr, *d_inv_ci = nullptr;
     double *d_tr_c = nullptr, *d_dscale = nullptr, *d_inv_cc = nullptr;
@@ -171,7 +172,7 @@ int upload(pbc_jk *h, T **p, const std::vector<T> &v)
 void release_device(pbc_jk *h)
 {
     void **pp[] = {(void **)&h->d_pairs, (void **)&h->d_groups, (void **)&h->d_boys, (void **)&h->d_bexp, (void **)&h->d_S,
-                   (void **)&h->d_G, (void **)&h->d_Gw, (void **)&h->d_sp_start, (void **)&h->d_sp_pairs,
+                   (void **)&h->d_G, (void **)&h->d_Gw, (void **)&h->d_Gs, (void **)&h->d_sp_start, (void **)&h->d_sp_pairs,
                    (void **)&h->d_sp_shA, (void **)&h->d_sp_shB, (void **)&h->d_sh_l, (void **)&h->d_sh_aoc,
                    (void **)&h->d_tr_ao, (void **)&h->d_inv_ci, (void **)&h->d_tr_c, (void **)&h->d_dscale,
                    (void **)&h->d_inv_cc, (void **)&h->d_D, (void **)&h->d_Dt, (void **)&h->d_Dmax,
@@ -253,6 +254,7 @@ int create_device(pbc_jk *h)
     if ((rc = upload(h, &h->d_S, S.S))) return rc;
     if ((rc = upload(h, &h->d_G, S.G))) return rc;
     if ((rc = upload(h, &h->d_Gw, S.Gw))) return rc;
+    if ((rc = upload(h, &h->d_Gs, S.Gs))) return rc;
     if ((rc = upload(h, &h->d_sp_start, S.sp_start))) return rc;
     if ((rc = upload(h, &h->d_sp_pairs, S.sp_pairs))) return rc;
     if ((rc = upload(h, &h->d_sp_shA, S.sp_shA))) return rc;
@@ -436,6 +438,26 @@ int blas_lowrank_stage1(pbc_jk *h, hipStream_t st, int n, int rank, int nb)
     return 0;
 }
 
+// Split reduction of K = sum_b Y_b Y_b^T over nc chunks of `per` consecutive
+// Y_b (a chunk is one n x (per rank) column-major matrix with ld n, since the
+// Y_b sit one after another): chunk c gives Y_c Y_c^T.  One chunk is added
+// straight into K; otherwise chunk c's product goes to P + c n^2.
+int blas_lowrank_stage2(pbc_jk *h, hipStream_t st, int n, int rank, int per, int nc, double *P)
+{
+    rocblas_handle bh = thread_blas();
+    if (!bh) return fail(PBC_JK_EDEVICE, "rocblas_create_handle failed");
+    if (rocblas_set_stream(bh, st) != rocblas_status_success) return fail(PBC_JK_EDEVICE, "rocblas_set_stream failed");
+    const double one = 1.0, zero = 0.0;
+    const long kc = (long)per * rank;
+    double *C = nc == 1 ? h->d_Kt : P;
+    const rocblas_status rs = rocblas_dgemm_strided_batched(
+        bh, rocblas_operation_none, rocblas_operation_transpose, n, n, (rocblas_int)kc, &one, h->d_T, n,
+        (rocblas_stride)kc * n, h->d_T, n, (rocblas_stride)kc * n, nc == 1 ? &one : &zero, C, n,
+        (rocblas_stride)n * n, nc);
+    if (rs != rocblas_status_success) return fail(PBC_JK_EDEVICE, "rocblas_dgemm_strided_batched failed");
+    return 0;
+}
+
 int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, double *E_K, hipStream_t st)
 {
     Setup &S = h->S;
@@ -532,11 +554,14 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
 
     // B5/B6: reciprocal-space J and K
     const int nG = (int)S.Gw.size();
+    // Kt holds full matrices (low-rank exchange) or only the upper output
+    // tiles of launch_dgemm (dense exchange, self term)
+    bool kt_full = false;
     if ((h->parts & PBC_JK_PART_LR) && nG > 0 && (wantJ || wantK)) {
         SfacArgs sa{};
         sa.pairs = h->d_pairs; sa.sp_start = h->d_sp_start; sa.sp_pairs = h->d_sp_pairs;
         sa.sp_shA = h->d_sp_shA; sa.sp_shB = h->d_sp_shB; sa.sh_l = h->d_sh_l; sa.sh_aoc = h->d_sh_aoc;
-        sa.F = h->d_F; sa.nbfc = n;
+        sa.F = h->d_F; sa.nbfc = n; sa.Gs = nullptr;
         const int ntile = (n + kGemmTile - 1) / kGemmTile, upper_tiles = ntile * (ntile + 1) / 2;
         const int rmax = h->lr_rmax;
         const bool lowrank = wantK && h->lr_mode == PBC_JK_LR_AUTO;
@@ -564,11 +589,12 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
         }
         const bool use_lr = lowrank && !h->h_ctl[1];
         const int rank = use_lr ? h->h_ctl[0] : 0;
+        kt_full = use_lr;
         if (lowrank && h->profile && h->last_rslot < h->ntimed) h->tflops[h->last_rslot] = 2.0 * (double)n * n * h->h_ctl[0];
         for (int g0 = 0; g0 < nG; g0 += h->gchunk) {
             const int gc = std::min(h->gchunk, nG - g0);
             HIPCHK(launch_fill(h->d_F, 2L * gc * n2, 0.0, st));
-            sa.G = h->d_G + 3 * g0; sa.ng = gc;
+            sa.G = h->d_G + 3 * g0; sa.Gs = h->d_Gs + g0; sa.ng = gc;
             {
                 TimedLaunch tl(h, st, 1, 0.0);
                 for (int c = 0; c < kNumClass; ++c) {
@@ -579,30 +605,36 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
             }
             if (wantJ) {
                 HIPCHK(launch_dot_batched(h->d_F, h->d_Dt, (int)n2, 2 * gc, h->d_rho, st));
-                HIPCHK(launch_jlr(h->d_F, h->d_rho, h->d_Gw + g0, gc, (int)n2, h->d_Jt, st));
+                HIPCHK(launch_jlr(h->d_F, h->d_rho, nullptr, gc, (int)n2, h->d_Jt, st));
             }
             if (wantK) {
                 const double nd = (double)n;
                 if (use_lr && rank > 0) {
-                    // Y_b = F_b L (rocBLAS, column-major: Y_b is n x rank, ld n), then
-                    // K += W_b Y_b Y_b^T on the upper output tiles
+                    // F_b carries sqrt(W_b), so K += sum_b Y_b Y_b^T with Y_b = F_b L
+                    // (rocBLAS, column-major: Y_b is n x rank, ld n)
+                    const int nb = 2 * gc;
                     {
-                        TimedLaunch tl(h, st, 30, 2.0 * nd * nd * rank * 2 * gc);
-                        const int brc = blas_lowrank_stage1(h, st, n, rank, 2 * gc);
+                        TimedLaunch tl(h, st, 30, 2.0 * nd * nd * rank * nb);
+                        const int brc = blas_lowrank_stage1(h, st, n, rank, nb);
                         if (brc) return brc;
                     }
-                    for (int half = 0; half < 2; ++half) {
-                        GemmArgs g2{};
-                        g2.M = g2.N = n; g2.K = rank;
-                        g2.A = h->d_T + (long)half * gc * n * rank; g2.lda = n; g2.sA = (long)n * rank; g2.transA = 1;
-                        g2.B = g2.A; g2.ldb = n; g2.sB = (long)n * rank;
-                        g2.C = h->d_Kt; g2.ldc = n; g2.sC = 0;
-                        g2.nbatch = gc; g2.alpha = h->d_Gw + g0; g2.alpha0 = 1.0; g2.reduce = 1; g2.upper = 1;
-                        g2.slices = std::max(1, std::min(gc, 2048 / std::max(1, upper_tiles)));
-                        g2.tag = 1;
-                        TimedLaunch tl(h, st, 2, nd * (nd + 1.0) * rank * g2.nbatch);
-                        HIPCHK(launch_dgemm(g2, st));
+                    // chunks of `per` Y_b, enough of them to fill the device with
+                    // output tiles; the last chunk is padded with zero Y_b when the
+                    // buffer has room, else everything goes into one product
+                    const long tiles = (long)((n + 127) / 128) * ((n + 127) / 128);
+                    int nc = (int)std::max(1L, std::min<long>(nb, (kStage2Tiles + tiles - 1) / tiles));
+                    int per = (nb + nc - 1) / nc;
+                    nc = (nb + per - 1) / per;
+                    const size_t tcap = std::max<size_t>((size_t)nb * n2, n2);
+                    if (nc > 1 && (size_t)nc * per * n * rank > tcap) { nc = 1; per = nb; }
+                    if (nc * per > nb)
+                        HIPCHK(launch_fill(h->d_T + (long)nb * n * rank, (long)(nc * per - nb) * n * rank, 0.0, st));
+                    {
+                        TimedLaunch tl(h, st, 31, nd * (nd + 1.0) * rank * nb);
+                        const int brc = blas_lowrank_stage2(h, st, n, rank, per, nc, h->d_F);
+                        if (brc) return brc;
                     }
+                    if (nc > 1) HIPCHK(launch_sum_partials(h->d_F, nc, n2, h->d_Kt, st));
                 } else if (!use_lr) {
                     // dense form: T_b = F_b D, K += W_b T_b F_b on the upper tiles (F_b symmetric)
                     GemmArgs g1{};
@@ -621,7 +653,7 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
                         g2.A = h->d_T + (long)half * gc * n2; g2.lda = n; g2.sA = n2;
                         g2.B = h->d_F + (long)half * gc * n2; g2.ldb = n; g2.sB = n2;
                         g2.C = h->d_Kt; g2.ldc = n; g2.sC = 0;
-                        g2.nbatch = gc; g2.alpha = h->d_Gw + g0; g2.alpha0 = 1.0; g2.reduce = 1; g2.upper = 1;
+                        g2.nbatch = gc; g2.alpha = nullptr; g2.alpha0 = 1.0; g2.reduce = 1; g2.upper = 1;
                         g2.slices = std::max(1, std::min(gc, 2048 / std::max(1, upper_tiles)));
                         TimedLaunch tl(h, st, 0, nd * (nd + 1.0) * nd * g2.nbatch);
                         HIPCHK(launch_dgemm(g2, st));
@@ -653,7 +685,7 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
                 HIPCHK(launch_dgemm(g1, st));
             }
             GemmArgs g2 = g1;
-            g2.A = h->d_T; g2.B = h->d_S; g2.C = h->d_Kt; g2.alpha0 = f; g2.reduce = 1; g2.upper = 1;
+            g2.A = h->d_T; g2.B = h->d_S; g2.C = h->d_Kt; g2.alpha0 = f; g2.reduce = 1; g2.upper = kt_full ? 0 : 1;
             {
                 TimedLaunch tg(h, st, 0, nd * (nd + 1.0) * nd);
                 HIPCHK(launch_dgemm(g2, st));
@@ -667,7 +699,7 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
         HIPCHK(launch_final(fa, st));
     }
     if (wantK) {
-        FinalArgs fa{h->d_Y, h->d_Kt, n, nb, 1, h->d_inv_ci, h->d_inv_cc, Ko};
+        FinalArgs fa{h->d_Y, h->d_Kt, n, nb, kt_full ? 0 : 1, h->d_inv_ci, h->d_inv_cc, Ko};
         HIPCHK(launch_final(fa, st));
     }
     if (E_J || E_K) {
@@ -914,9 +946,9 @@ int pbc_jk_stats(const pbc_jk *hc, pbc_jk_counters *out)
         const bool dense = !h->lr_ran || ctl[1];
         h->st.lr_rank = dense ? -1.0 : (double)ctl[0];
         // the GEMM figures describe the kernel that accumulated the exchange:
-        // k_dgemm<1> (low rank) or k_dgemm<0> (dense form, with the self term)
-        const int main_kind = dense ? 0 : 2;
-        h->st.gemm_kernel = dense ? 0 : 1;
+        // rocBLAS Y Y^T (low rank) or k_dgemm<0> (dense form, with the self term)
+        const int main_kind = dense ? 0 : 31;
+        h->st.gemm_kernel = dense ? 0 : 2;
         h->st.t_gemm_ms = h->st.t_sfac_ms = h->st.gemm_flops = h->st.t_chol_ms = 0.0;
         h->st.t_blas_ms = h->st.blas_flops = 0.0;
         h->st.n_gemm = h->st.n_blas = 0;
@@ -935,8 +967,8 @@ int pbc_jk_stats(const pbc_jk *hc, pbc_jk_counters *out)
                 h->st.n_blas++;
             } else if (kind == 1) {
                 h->st.t_sfac_ms += ms;
-            } else if (kind == 4) {
-                h->st.t_chol_ms += ms;
+            } else if (kind == 4 || kind == 2) {
+                h->st.t_chol_ms += ms;   // factorisation and its residual check
             } else if (kind >= 5 && kind < 26) {
                 h->st.t_sr_class_ms[kind - 5] += ms;
             }

@@ -82,6 +82,7 @@ struct Setup {
     std::vector<GroupRec> groups;
     int class_start[kNumClass + 1] = {0};   // group ranges per class
     std::vector<double> G;          // 3 * nG, half space
+    std::vector<double> Gs;         // nG: sqrt of the weights (F_G is stored scaled by it)
     std::vector<double> Gw;         // 2 w_G (both signs folded)
     std::vector<double> S;          // scaled-Cartesian Gamma overlap, nbfc^2
     std::vector<double> boys;       // kBoysNT * kBoysM

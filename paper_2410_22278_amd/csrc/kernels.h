@@ -84,6 +84,7 @@ struct SfacArgs {
     const int *sh_l, *sh_aoc;
     int sp0, nsp;         // shell-pair range of one class
     const double *G;      // 3 * ng
+    const double *Gs;     // ng scale factors applied to F_G (sqrt of the weights), or NULL
     int ng;
     double *F;            // 2 ng x nbfc x nbfc
     int nbfc;
@@ -94,6 +95,9 @@ hipError_t launch_sfac(int cls, const SfacArgs &a, hipStream_t st);
 hipError_t launch_dot_batched(const double *F, const double *Dt, int n2, int nb, double *rho, hipStream_t st);
 
 // Jt[mu nu] += sum_g Gw[g] (F[g][mu nu] rho[g] + F[ng+g][mu nu] rho[ng+g]).
+// K[i] += sum_c P[c][i] for c < nc.
+hipError_t launch_sum_partials(const double *P, int nc, long n2, double *K, hipStream_t st);
+// Jt += sum_g Gw[g] (Re F_g rho_g + Im F_g rho'_g); Gw NULL: unit weights.
 hipError_t launch_jlr(const double *F, const double *rho, const double *Gw, int ng, int n2, double *Jt,
                       hipStream_t st);
 

@@ -90,6 +90,13 @@ __device__ __forceinline__ void sfac_store(const SfacArgs &a, int sp, int g, dou
     constexpr int NA = ncart(LA), NB = ncart(LB);
     double re[NA][NB], im[NA][NB];
     sfac_pairs<LA, LB>(a, sp, Gx, Gy, Gz, re, im);
+    if (a.Gs) {
+        const double w = a.Gs[g];
+#pragma unroll
+        for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+            for (int ib = 0; ib < NB; ++ib) { re[ia][ib] *= w; im[ia][ib] *= w; }
+    }
     const int A = a.sp_shA[sp], B = a.sp_shB[sp];
     const long n = a.nbfc;
     double *Fr = a.F + (long)g * n * n;
@@ -168,8 +175,18 @@ __global__ __launch_bounds__(256) void k_jlr(const double *F, const double *rho,
     if (i >= n2) return;
     double s = 0.0;
     for (int g = 0; g < ng; ++g)
-        s += Gw[g] * (F[(long)g * n2 + i] * rho[g] + F[(long)(ng + g) * n2 + i] * rho[ng + g]);
+        s += (Gw ? Gw[g] : 1.0) * (F[(long)g * n2 + i] * rho[g] + F[(long)(ng + g) * n2 + i] * rho[ng + g]);
     Jt[i] += s;
+}
+
+// K[i] += sum_c P[c][i], c < nc (partial products of the split reduction)
+__global__ __launch_bounds__(256) void k_sum_partials(const double *P, int nc, long n2, double *K)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += (long)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int c = 0; c < nc; ++c) s += P[(long)c * n2 + i];
+        K[i] += s;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_fill(double *p, long n, double v)
@@ -692,6 +709,14 @@ hipError_t launch_dot_batched(const double *F, const double *Dt, int n2, int nb,
 {
     if (nb <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_dot_batched, dim3(nb), dim3(256), 0, st, F, Dt, (long)n2, rho);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_partials(const double *P, int nc, long n2, double *K, hipStream_t st)
+{
+    if (nc <= 0 || n2 <= 0) return hipSuccess;
+    const long blocks = std::min<long>(4096, (n2 + 255) / 256);
+    hipLaunchKernelGGL(k_sum_partials, dim3((unsigned)blocks), dim3(256), 0, st, P, nc, n2, K);
     return hipGetLastError();
 }
 

@@ -422,7 +422,7 @@ int build_setup(const double *cell, int natom, const double *xyz, int nshell, co
             for (int j = 0; j < 3; ++j) Binv[3 * i + j] = L.M[3 * j + i] / (2.0 * kPi);
         for (int j = 0; j < 3; ++j) bspan[j] = std::fabs(Binv[j]) + std::fabs(Binv[3 + j]) + std::fabs(Binv[6 + j]);
         double zero[3] = {0, 0, 0};
-        S.G.clear(); S.Gw.clear();
+        S.G.clear(); S.Gw.clear(); S.Gs.clear();
         for_lattice_box(L.B, Binv, bspan, zero, r, [&](const double Gv[3], int n0, int n1, int n2) {
             bool pos = n0 > 0 || (n0 == 0 && (n1 > 0 || (n1 == 0 && n2 > 0)));
             if (!pos) return;
@@ -432,6 +432,7 @@ int build_setup(const double *cell, int natom, const double *xyz, int nshell, co
             if (S.g_cut > 0 && G2 > S.g_cut * S.g_cut) return;
             S.G.push_back(Gv[0]); S.G.push_back(Gv[1]); S.G.push_back(Gv[2]);
             S.Gw.push_back(2.0 * w);
+            S.Gs.push_back(std::sqrt(2.0 * w));
         });
     }
 
