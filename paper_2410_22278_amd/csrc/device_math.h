@@ -105,6 +105,19 @@ __device__ __forceinline__ double fast_rsqrt(double x)
     return y * fma(-h * y, y, 1.5);
 }
 
+// Natural logarithm for screening radii only: exponent by frexp, log2 of the
+// mantissa from the FP32 hardware logarithm, plus 1e-6, which bounds the
+// error of the rest (about 1.5e-7 absolute), so the result is never below
+// ln x.  A radius from it is at least the exact one and larger by a relative
+// 1e-6 / ln(x) at most, so a screen built on it keeps every term the exact
+// screen keeps and adds only terms at the threshold.
+__device__ __forceinline__ double screen_log(double x)
+{
+    const int e = __builtin_amdgcn_frexp_exp(x);
+    const float m = (float)__builtin_amdgcn_frexp_mant(x);   // [0.5, 1)
+    return ((double)e + (double)__builtin_amdgcn_logf(m)) * 0.69314718055994530942 + 1e-6;
+}
+
 // F_m(T), m = 0..L, FP64.  tab: LDS copy of rows L..L+kBoysTerms-1,
 // layout [k][j].  Below kBoysTmax: Taylor expansion of F_L about the
 // nearest grid point, then downward recursion; above: asymptotic F_0 and
@@ -144,7 +157,9 @@ __device__ __forceinline__ void boys_f64(double T, const double *__restrict__ ta
         F[0] = 0.88622692545275801365 * rs;   // sqrt(pi)/2 / sqrt(T)
         if (L > 0) {
             const double it = rs * rs;
-            double e = exp(-T);
+            // above kBoysTmax e^{-T} changes F_m, m <= 8, by a relative 3e-8 at
+            // most, so its FP32 value (hardware exp2) is ample
+            const double e = (double)__builtin_amdgcn_exp2f((float)(-1.44269504088896340736 * T));
 #pragma unroll
             for (int m = 0; m < L; ++m) F[m + 1] = ((2 * m + 1) * F[m] - e) * (0.5 * it);
         }
@@ -252,7 +267,7 @@ __device__ __forceinline__ bool quartet_sphere(const PairRec &b, const PairRec &
     const double C2e = b.Cb * k.Cb * kTwoPi52 * ip * iq * fast_rsqrt(p + q);
     const double arg = C2e * (1.0 - c) * fast_rcp(dR);
     if (!(arg > 1.0)) return false;
-    rad2 = (ip + iq + fast_rcp(w2)) * log(arg);
+    rad2 = (ip + iq + fast_rcp(w2)) * screen_log(arg);
     return true;
 }
 
