@@ -358,6 +358,9 @@ def main():
         "E_K": EK,
         "roofline": roof_main,
         "roofline_secondary": roof2,
+        "sr_classes": [{"class_pair": f"({CLASS_NAMES[SLOTS[k][0]]}|{CLASS_NAMES[SLOTS[k][1]]})",
+                        "ms_per_build": sr_class_ms[k] / steps, "terms_per_build": sr_terms_class[k] / steps}
+                       for k in range(21) if sr_class_ms[k] > 0],
         "sr_all_classes": {"ms_per_build": sr_total_ms,
                            "achieved_tflops": sr_total_fl / (sr_total_ms * 1e-3) / 1e12 if sr_total_ms > 0 else 0.0,
                            "frac_fp64_valu": (sr_total_fl / (sr_total_ms * 1e-3) / 1e12 / FP64_VALU_PEAK_TFLOPS

@@ -12,6 +12,25 @@ namespace pbcjk {
 
 namespace {
 
+// Pair records seen through the constant address space (read-only for the
+// whole kernel), so that loads at wavefront-uniform addresses go through the
+// scalar unit.
+typedef const __attribute__((address_space(4))) PairRec *CPairPtr;
+
+__device__ __forceinline__ PairRec load_pair(const PairRec *p) { return *p; }
+__device__ __forceinline__ PairRec load_pair(CPairPtr p)
+{
+    PairRec r;
+#pragma unroll
+    for (int x = 0; x < 3; ++x) {
+        r.P[x] = p->P[x];
+        r.PA[x] = p->PA[x];
+        r.PB[x] = p->PB[x];
+        r.pad[x] = p->pad[x];
+    }
+    r.p = p->p; r.cpre = p->cpre; r.Q = p->Q; r.Cb = p->Cb;
+    return r;
+}
 
 // acc += pref * sum_t E^ab_t sum_s (-1)^|s| E^cd_s R_{t+s}  (ket transform
 // first, then the bra), evaluated in the value type V.
@@ -203,101 +222,112 @@ void k_sr_jk(SRArgs a)
 #pragma unroll
                     for (int i3 = 0; i3 < ND; ++i3) acc[i0][i1][i2][i3] = 0.0;
         unsigned long long ent_terms = 0;
-        // group-level density screen (already applied when the list was compacted)
-
-        // ket pairs outer (each lane reads its own ket records once), bra pairs
-        // inner (the wavefront's lanes mostly share the bra group, so those
-        // loads are broadcast from cache)
-        const int pk_end = (gb.Qmax * gk.Qmax * wD > a.d_schwarz) ? gk.pend : gk.pstart;
-        for (int pk = gk.pstart; pk < pk_end; ++pk) {
-            const PairRec Pk = a.pairs[pk];
-            EAxis<LC, LD> Fx, Fy, Fz;
-            const double hk = 0.5 * Pk.pad[0];
-            herm_axis<LC, LD>(hk, Pk.PA[0], Pk.PB[0], Fx);
-            herm_axis<LC, LD>(hk, Pk.PA[1], Pk.PB[1], Fy);
-            herm_axis<LC, LD>(hk, Pk.PA[2], Pk.PB[2], Fz);
-            for (int pb = gb.pstart; pb < gb.pend; ++pb) {
-                const PairRec Pb = a.pairs[pb];
-                if (!(Pb.Q * Pk.Q * wD > a.d_schwarz)) continue;
-                ++cnt_q;
-                double rad2;
-                if (!quartet_sphere(Pb, Pk, a.w2, a.d_ewald_R, rad2)) continue;
-                const double p = Pb.p, q = Pk.p;
-                const double rho = fast_rcp(Pb.pad[0] + Pk.pad[0]);
-                const double pref = Pb.cpre * Pk.cpre * kTwoPi52 * Pb.pad[0] * Pk.pad[0] * fast_rsqrt(p + q);
-                EAxis<LA, LB> Ex, Ey, Ez;
-                const double hb = 0.5 * Pb.pad[0];
-                herm_axis<LA, LB>(hb, Pb.PA[0], Pb.PB[0], Ex);
-                herm_axis<LA, LB>(hb, Pb.PA[1], Pb.PB[1], Ey);
-                herm_axis<LA, LB>(hb, Pb.PA[2], Pb.PB[2], Ez);
-                const double cen[3] = {Pb.P[0] - Pk.P[0], Pb.P[1] - Pk.P[1], Pb.P[2] - Pk.P[2]};
-                if (FOLD) {
-                    // lattice sum of the Hermite integrals in FP64, one transform
-                    double Rs[L + 1][L + 1][L + 1];
-#pragma unroll
-                    for (int t = 0; t <= L; ++t)
-#pragma unroll
-                        for (int u = 0; u <= L - t; ++u)
-#pragma unroll
-                            for (int v = 0; v <= L - t - u; ++v) Rs[t][u][v] = 0.0;
-                    int nimg = 0;
-                    for_images(a.lat, cen, rad2, a.rcap2, [&](const double *Lv, double L2) {
-                        ++nimg;
-                        if (F32) {
-                            float R0[L + 1];
-                            sr_R0_mixed<L>(rho, a.w2, L2, tab, etab, R0);
-                            float R[L + 1][L + 1][L + 1];
-                            herm_R<L, float>(R0, (float)Lv[0], (float)Lv[1], (float)Lv[2], R);
-#pragma unroll
-                            for (int t = 0; t <= L; ++t)
-#pragma unroll
-                                for (int u = 0; u <= L - t; ++u)
-#pragma unroll
-                                    for (int v = 0; v <= L - t - u; ++v) Rs[t][u][v] += (double)R[t][u][v];
-                        } else {
-                            double R0[L + 1];
-                            sr_R0<L, kBoysTerms, true>(rho, a.w2, L2, tab, etab, R0);
-                            double R[L + 1][L + 1][L + 1];
-                            herm_R<L, double>(R0, Lv[0], Lv[1], Lv[2], R);
-#pragma unroll
-                            for (int t = 0; t <= L; ++t)
-#pragma unroll
-                                for (int u = 0; u <= L - t; ++u)
-#pragma unroll
-                                    for (int v = 0; v <= L - t - u; ++v) Rs[t][u][v] += R[t][u][v];
-                        }
-                    });
-                    if (nimg == 0) continue;
-                    cnt_t += nimg;
-                    ent_terms += nimg;
-                    V Rv[L + 1][L + 1][L + 1];
-#pragma unroll
-                    for (int t = 0; t <= L; ++t)
-#pragma unroll
-                        for (int u = 0; u <= L - t; ++u)
-#pragma unroll
-                            for (int v = 0; v <= L - t - u; ++v) Rv[t][u][v] = (V)Rs[t][u][v];
-                    add_term<LA, LB, LC, LD, V, IC0, NIC>(Ex, Ey, Ez, Fx, Fy, Fz, Rv, pref, acc);
-                } else {
-                    for_images(a.lat, cen, rad2, a.rcap2, [&](const double *Lv, double L2) {
-                        ++cnt_t;
-                        ++ent_terms;
-                        if (F32) {
-                            float R0[L + 1];
-                            sr_R0_mixed<L>(rho, a.w2, L2, tab, etab, R0);
-                            float R[L + 1][L + 1][L + 1];
-                            herm_R<L, float>(R0, (float)Lv[0], (float)Lv[1], (float)Lv[2], R);
-                            add_term<LA, LB, LC, LD, float, IC0, NIC>(Ex, Ey, Ez, Fx, Fy, Fz, R, pref, acc);
-                        } else {
-                            double R0[L + 1];
-                            sr_R0<L, kBoysTerms, true>(rho, a.w2, L2, tab, etab, R0);
-                            double R[L + 1][L + 1][L + 1];
-                            herm_R<L, double>(R0, Lv[0], Lv[1], Lv[2], R);
-                            add_term<LA, LB, LC, LD, double, IC0, NIC>(Ex, Ey, Ez, Fx, Fy, Fz, R, pref, acc);
-                        }
-                    });
+        // Ket pairs outer (each lane reads its own ket records once), bra pairs
+        // inner.  A group's pairs are stored by descending Q, so the first pair
+        // that fails the Cauchy-Schwarz test ends its loop.  When every lane of
+        // the wavefront has the same bra group (the usual case: the lists run
+        // in bra order), the bra records are read through the constant address
+        // space, so their loads are scalar and the bra loop is uniform.
+        auto run = [&](auto bpairs, int pbs, int pbe) {
+            const int pk_end = (gb.Qmax * gk.Qmax * wD > a.d_schwarz) ? gk.pend : gk.pstart;
+            for (int pk = gk.pstart; pk < pk_end; ++pk) {
+                const PairRec Pk = a.pairs[pk];
+                if (!(gb.Qmax * Pk.Q * wD > a.d_schwarz)) break;
+                EAxis<LC, LD> Fx, Fy, Fz;
+                const double hk = 0.5 * Pk.pad[0];
+                herm_axis<LC, LD>(hk, Pk.PA[0], Pk.PB[0], Fx);
+                herm_axis<LC, LD>(hk, Pk.PA[1], Pk.PB[1], Fy);
+                herm_axis<LC, LD>(hk, Pk.PA[2], Pk.PB[2], Fz);
+                for (int pb = pbs; pb < pbe; ++pb) {
+                    const PairRec Pb = load_pair(bpairs + pb);
+                    if (!(Pb.Q * Pk.Q * wD > a.d_schwarz)) break;
+                    ++cnt_q;
+                    double rad2;
+                    if (!quartet_sphere(Pb, Pk, a.w2, a.d_ewald_R, rad2)) continue;
+                    const double p = Pb.p, q = Pk.p;
+                    const double rho = fast_rcp(Pb.pad[0] + Pk.pad[0]);
+                    const double pref = Pb.cpre * Pk.cpre * kTwoPi52 * Pb.pad[0] * Pk.pad[0] * fast_rsqrt(p + q);
+                    EAxis<LA, LB> Ex, Ey, Ez;
+                    const double hb = 0.5 * Pb.pad[0];
+                    herm_axis<LA, LB>(hb, Pb.PA[0], Pb.PB[0], Ex);
+                    herm_axis<LA, LB>(hb, Pb.PA[1], Pb.PB[1], Ey);
+                    herm_axis<LA, LB>(hb, Pb.PA[2], Pb.PB[2], Ez);
+                    const double cen[3] = {Pb.P[0] - Pk.P[0], Pb.P[1] - Pk.P[1], Pb.P[2] - Pk.P[2]};
+                    if (FOLD) {
+                        // lattice sum of the Hermite integrals in FP64, one transform
+                        double Rs[L + 1][L + 1][L + 1];
+    #pragma unroll
+                        for (int t = 0; t <= L; ++t)
+    #pragma unroll
+                            for (int u = 0; u <= L - t; ++u)
+    #pragma unroll
+                                for (int v = 0; v <= L - t - u; ++v) Rs[t][u][v] = 0.0;
+                        int nimg = 0;
+                        for_images(a.lat, cen, rad2, a.rcap2, [&](const double *Lv, double L2) {
+                            ++nimg;
+                            if (F32) {
+                                float R0[L + 1];
+                                sr_R0_mixed<L>(rho, a.w2, L2, tab, etab, R0);
+                                float R[L + 1][L + 1][L + 1];
+                                herm_R<L, float>(R0, (float)Lv[0], (float)Lv[1], (float)Lv[2], R);
+    #pragma unroll
+                                for (int t = 0; t <= L; ++t)
+    #pragma unroll
+                                    for (int u = 0; u <= L - t; ++u)
+    #pragma unroll
+                                        for (int v = 0; v <= L - t - u; ++v) Rs[t][u][v] += (double)R[t][u][v];
+                            } else {
+                                double R0[L + 1];
+                                sr_R0<L, kBoysTerms, true>(rho, a.w2, L2, tab, etab, R0);
+                                double R[L + 1][L + 1][L + 1];
+                                herm_R<L, double>(R0, Lv[0], Lv[1], Lv[2], R);
+    #pragma unroll
+                                for (int t = 0; t <= L; ++t)
+    #pragma unroll
+                                    for (int u = 0; u <= L - t; ++u)
+    #pragma unroll
+                                        for (int v = 0; v <= L - t - u; ++v) Rs[t][u][v] += R[t][u][v];
+                            }
+                        });
+                        if (nimg == 0) continue;
+                        cnt_t += nimg;
+                        ent_terms += nimg;
+                        V Rv[L + 1][L + 1][L + 1];
+    #pragma unroll
+                        for (int t = 0; t <= L; ++t)
+    #pragma unroll
+                            for (int u = 0; u <= L - t; ++u)
+    #pragma unroll
+                                for (int v = 0; v <= L - t - u; ++v) Rv[t][u][v] = (V)Rs[t][u][v];
+                        add_term<LA, LB, LC, LD, V, IC0, NIC>(Ex, Ey, Ez, Fx, Fy, Fz, Rv, pref, acc);
+                    } else {
+                        for_images(a.lat, cen, rad2, a.rcap2, [&](const double *Lv, double L2) {
+                            ++cnt_t;
+                            ++ent_terms;
+                            if (F32) {
+                                float R0[L + 1];
+                                sr_R0_mixed<L>(rho, a.w2, L2, tab, etab, R0);
+                                float R[L + 1][L + 1][L + 1];
+                                herm_R<L, float>(R0, (float)Lv[0], (float)Lv[1], (float)Lv[2], R);
+                                add_term<LA, LB, LC, LD, float, IC0, NIC>(Ex, Ey, Ez, Fx, Fy, Fz, R, pref, acc);
+                            } else {
+                                double R0[L + 1];
+                                sr_R0<L, kBoysTerms, true>(rho, a.w2, L2, tab, etab, R0);
+                                double R[L + 1][L + 1][L + 1];
+                                herm_R<L, double>(R0, Lv[0], Lv[1], Lv[2], R);
+                                add_term<LA, LB, LC, LD, double, IC0, NIC>(Ex, Ey, Ez, Fx, Fy, Fz, R, pref, acc);
+                            }
+                        });
+                    }
                 }
             }
+        };
+        const int bi0 = __builtin_amdgcn_readfirstlane(bi);
+        if (__builtin_amdgcn_ballot_w64(bi != bi0) == 0) {
+            const CPairPtr cp = (CPairPtr)a.pairs;
+            run(cp, __builtin_amdgcn_readfirstlane(gb.pstart), __builtin_amdgcn_readfirstlane(gb.pend));
+        } else {
+            run(a.pairs, gb.pstart, gb.pend);
         }
         if (ent_terms > 0) {
             const double w = (a.tri && j == bi) ? 0.5 : 1.0;
