@@ -175,7 +175,7 @@ __device__ __forceinline__ void scatter_block(const SRArgs &a, const double (&ac
 // Class pairs with small blocks keep three wavefronts per SIMD (their
 // register use sits just above the two-wavefront line otherwise).
 template <int LA, int LB, int LC, int LD>
-constexpr int sr_waves_per_eu() { return (LA + LB + LC + LD <= 1) ? 3 : 1; }
+constexpr int sr_waves_per_eu() { return (LA + LB + LC + LD <= 1) ? 4 : (LA + LB + LC + LD == 2) ? 3 : (LA + LB + LC + LD == 3) ? 2 : 1; }
 
 template <int LA, int LB, int LC, int LD, typename V, bool FOLD, int IC0 = 0, int NIC = ncart(LC)>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sr_waves_per_eu<LA, LB, LC, LD>())))
