@@ -172,10 +172,16 @@ __device__ __forceinline__ void scatter_block(const SRArgs &a, const double (&ac
 // class pairs run one launch per slice so that the slice fits in registers,
 // each recomputing the shifts' Hermite integrals).  Counters are kept by the
 // slice that starts at component 0.
-// Class pairs with small blocks keep three wavefronts per SIMD (their
-// register use sits just above the two-wavefront line otherwise).
+// Wavefronts per SIMD asked of the register allocator, by total angular
+// momentum: these kernels wait on dependent FP64 chains (Horner steps, Newton
+// steps) and on loads, so more resident wavefronts pay even at the price of
+// a few spilled registers (L <= 3); from L = 4 on the spills cost more.
 template <int LA, int LB, int LC, int LD>
-constexpr int sr_waves_per_eu() { return (LA + LB + LC + LD <= 1) ? 4 : (LA + LB + LC + LD == 2) ? 3 : (LA + LB + LC + LD == 3) ? 2 : 1; }
+constexpr int sr_waves_per_eu()
+{
+    constexpr int L = LA + LB + LC + LD;
+    return L == 0 ? 5 : L == 1 ? 4 : L == 2 ? 3 : L == 3 ? 2 : 1;
+}
 
 template <int LA, int LB, int LC, int LD, typename V, bool FOLD, int IC0 = 0, int NIC = ncart(LC)>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sr_waves_per_eu<LA, LB, LC, LD>())))
