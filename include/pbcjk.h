@@ -120,7 +120,10 @@ typedef struct {
     double terms_fp32;   /* last build: of which in FP32                     */
     double t_setup_ms;   /* create wall time                                 */
     double t_build_ms;   /* last build wall time                             */
-    double t_sr_ms, t_lr_ms, t_other_ms; /* last build, device stage times   */
+    double t_sr_ms, t_lr_ms, t_other_ms; /* last build, device stage times: density
+                            preparation and short range on the build stream; reciprocal part
+                            and self term on a second stream of the handle, concurrently
+                            with the short range; final assembly after both              */
     double t_gemm_ms;    /* last build: summed durations of the launches of the GEMM kernel that
                             formed the reciprocal exchange (gemm_kernel), self term included
                             when that kernel is the plain one                                  */

@@ -106,7 +106,12 @@ struct pbc_jk {
     int class_max_pp[6] = {0};   // most primitive pairs in one group, per class
     bool coop_d[21] = {false};   // large d class pairs: one wavefront per group pair (else slices)
     int gchunk = 0;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    // the reciprocal part and the self term run on `side`, beside the short
+    // range on the build stream: fork after the density preparation, join
+    // before the final assembly
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // event pairs around GEMM and structure-factor launches of one build
     static constexpr int kMaxTimed = 256;
     std::vector<hipEvent_t> tev;
@@ -205,6 +210,11 @@ void release(pbc_jk *h)
     h->h_ctl = nullptr;
     if (h->own) (void)hipStreamDestroy(h->own);
     h->own = nullptr;
+    if (h->side) (void)hipStreamDestroy(h->side);
+    h->side = nullptr;
+    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+    if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+    h->ev_fork = h->ev_join = nullptr;
     for (auto &e : h->ev) e = nullptr;
     h->tev.clear();
 }
@@ -237,6 +247,9 @@ int create_device(pbc_jk *h)
     if (!h->dry) {
         HIPCHK(hipGetDevice(&h->device));
         if (!h->own) HIPCHK(hipStreamCreateWithFlags(&h->own, hipStreamNonBlocking));
+        if (!h->side) HIPCHK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+        if (!h->ev_fork) HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+        if (!h->ev_join) HIPCHK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
         for (auto &e : h->ev)
             if (!e) HIPCHK(hipEventCreate(&e));
         if (h->profile && h->tev.empty()) {
@@ -458,7 +471,7 @@ int blas_lowrank_stage2(pbc_jk *h, hipStream_t st, int n, int rank, int per, int
     return 0;
 }
 
-int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, double *E_K, hipStream_t st)
+int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, double *E_K, hipStream_t st)
 {
     Setup &S = h->S;
     const int n = S.nbfc, nb = S.nbf;
@@ -489,6 +502,11 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
                 h->coop_d[k] = nt > kCoopRatio * nq;
             }
         }
+
+    // the reciprocal part and the self term go to the side stream
+    hipStream_t ls = h->side;
+    HIPCHK(hipEventRecord(h->ev_fork, st));
+    HIPCHK(hipStreamWaitEvent(ls, h->ev_fork, 0));
 
     // B3/B4: short-range J and K.  Per class pair: the density-weighted
     // screen compacts the neighbour list into FP64 and FP32 work lists, then
@@ -552,60 +570,65 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
     }
     HIPCHK(hipEventRecord(h->ev[1], st));
 
-    // B5/B6: reciprocal-space J and K
+    // B6 prelude (side stream, beside the short range): the density factor of
+    // the low-rank exchange and its rank, read back to the host (one
+    // synchronisation, after the short range is queued).  Kt then holds full
+    // matrices (low-rank exchange) or only the upper output tiles of
+    // launch_dgemm (dense exchange, self term).
     const int nG = (int)S.Gw.size();
-    // Kt holds full matrices (low-rank exchange) or only the upper output
-    // tiles of launch_dgemm (dense exchange, self term)
-    bool kt_full = false;
-    if ((h->parts & PBC_JK_PART_LR) && nG > 0 && (wantJ || wantK)) {
+    const bool lr_on = (h->parts & PBC_JK_PART_LR) && nG > 0 && (wantJ || wantK);
+    HIPCHK(hipEventRecord(h->ev[4], ls));
+    const bool lowrank = lr_on && wantK && h->lr_mode == PBC_JK_LR_AUTO;
+    h->lr_ran = lowrank;
+    if (lowrank) {
+        // D~ = L L^T on the device; R = L L^T into T, then the entrywise check
+        TimedLaunch tl(h, ls, 4, 0.0);
+        HIPCHK(launch_pchol(h->d_Dt, n, h->lr_tol, h->lr_rmax, h->d_L, h->d_pw, h->d_pwi, h->d_ctl, h->h_ctl, ls));
+        GemmArgs gr{};
+        gr.M = gr.N = n; gr.K = h->lr_rmax;
+        gr.A = h->d_L; gr.lda = n; gr.sA = 0; gr.transA = 1;
+        gr.B = h->d_L; gr.ldb = n; gr.sB = 0;
+        gr.C = h->d_T; gr.ldc = n; gr.sC = 0;
+        gr.nbatch = 1; gr.alpha0 = 1.0; gr.slices = 1;
+        gr.ctl = h->d_ctl; gr.ctl_mode = 2;
+        h->last_rslot = h->ntimed;
+        {
+            TimedLaunch tg(h, ls, 2, 0.0);
+            HIPCHK(launch_dgemm(gr, ls));
+        }
+        HIPCHK(launch_lowrank_check(h->d_Dt, h->d_T, n, h->d_pw, h->d_ctl, ls));
+        // the factor's rank sizes the products below: read it back
+        HIPCHK(hipMemcpyAsync(h->h_ctl, h->d_ctl, 4 * sizeof(int), hipMemcpyDeviceToHost, ls));
+        HIPCHK(hipStreamSynchronize(ls));
+    }
+    const bool use_lr = lowrank && !h->h_ctl[1];
+    const int rank = use_lr ? h->h_ctl[0] : 0;
+    const bool kt_full = use_lr;
+    if (lowrank && h->profile && h->last_rslot < h->ntimed) h->tflops[h->last_rslot] = 2.0 * (double)n * n * h->h_ctl[0];
+
+
+    // B5/B6: reciprocal-space J and K (side stream)
+    if (lr_on) {
         SfacArgs sa{};
         sa.pairs = h->d_pairs; sa.sp_start = h->d_sp_start; sa.sp_pairs = h->d_sp_pairs;
         sa.sp_shA = h->d_sp_shA; sa.sp_shB = h->d_sp_shB; sa.sh_l = h->d_sh_l; sa.sh_aoc = h->d_sh_aoc;
         sa.F = h->d_F; sa.nbfc = n; sa.Gs = nullptr;
         const int ntile = (n + kGemmTile - 1) / kGemmTile, upper_tiles = ntile * (ntile + 1) / 2;
-        const int rmax = h->lr_rmax;
-        const bool lowrank = wantK && h->lr_mode == PBC_JK_LR_AUTO;
-        h->lr_ran = lowrank;
-        if (lowrank) {
-            // D~ = L L^T on the device; R = L L^T into T, then the entrywise check
-            TimedLaunch tl(h, st, 4, 0.0);
-            HIPCHK(launch_pchol(h->d_Dt, n, h->lr_tol, rmax, h->d_L, h->d_pw, h->d_pwi, h->d_ctl, h->h_ctl, st));
-            GemmArgs gr{};
-            gr.M = gr.N = n; gr.K = rmax;
-            gr.A = h->d_L; gr.lda = n; gr.sA = 0; gr.transA = 1;
-            gr.B = h->d_L; gr.ldb = n; gr.sB = 0;
-            gr.C = h->d_T; gr.ldc = n; gr.sC = 0;
-            gr.nbatch = 1; gr.alpha0 = 1.0; gr.slices = 1;
-            gr.ctl = h->d_ctl; gr.ctl_mode = 2;
-            h->last_rslot = h->ntimed;
-            {
-                TimedLaunch tg(h, st, 2, 0.0);
-                HIPCHK(launch_dgemm(gr, st));
-            }
-            HIPCHK(launch_lowrank_check(h->d_Dt, h->d_T, n, h->d_pw, h->d_ctl, st));
-            // the factor's rank sizes the products below: read it back
-            HIPCHK(hipMemcpyAsync(h->h_ctl, h->d_ctl, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
-            HIPCHK(hipStreamSynchronize(st));
-        }
-        const bool use_lr = lowrank && !h->h_ctl[1];
-        const int rank = use_lr ? h->h_ctl[0] : 0;
-        kt_full = use_lr;
-        if (lowrank && h->profile && h->last_rslot < h->ntimed) h->tflops[h->last_rslot] = 2.0 * (double)n * n * h->h_ctl[0];
         for (int g0 = 0; g0 < nG; g0 += h->gchunk) {
             const int gc = std::min(h->gchunk, nG - g0);
-            HIPCHK(launch_fill(h->d_F, 2L * gc * n2, 0.0, st));
+            HIPCHK(launch_fill(h->d_F, 2L * gc * n2, 0.0, ls));
             sa.G = h->d_G + 3 * g0; sa.Gs = h->d_Gs + g0; sa.ng = gc;
             {
-                TimedLaunch tl(h, st, 1, 0.0);
+                TimedLaunch tl(h, ls, 1, 0.0);
                 for (int c = 0; c < kNumClass; ++c) {
                     sa.sp0 = S.sp_class_start[c];
                     sa.nsp = S.sp_class_start[c + 1] - S.sp_class_start[c];
-                    HIPCHK(launch_sfac(c, sa, st));
+                    HIPCHK(launch_sfac(c, sa, ls));
                 }
             }
             if (wantJ) {
-                HIPCHK(launch_dot_batched(h->d_F, h->d_Dt, (int)n2, 2 * gc, h->d_rho, st));
-                HIPCHK(launch_jlr(h->d_F, h->d_rho, nullptr, gc, (int)n2, h->d_Jt, st));
+                HIPCHK(launch_dot_batched(h->d_F, h->d_Dt, (int)n2, 2 * gc, h->d_rho, ls));
+                HIPCHK(launch_jlr(h->d_F, h->d_rho, nullptr, gc, (int)n2, h->d_Jt, ls));
             }
             if (wantK) {
                 const double nd = (double)n;
@@ -614,8 +637,8 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
                     // (rocBLAS, column-major: Y_b is n x rank, ld n)
                     const int nb = 2 * gc;
                     {
-                        TimedLaunch tl(h, st, 30, 2.0 * nd * nd * rank * nb);
-                        const int brc = blas_lowrank_stage1(h, st, n, rank, nb);
+                        TimedLaunch tl(h, ls, 30, 2.0 * nd * nd * rank * nb);
+                        const int brc = blas_lowrank_stage1(h, ls, n, rank, nb);
                         if (brc) return brc;
                     }
                     // chunks of `per` Y_b, enough of them to fill the device with
@@ -628,13 +651,13 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
                     const size_t tcap = std::max<size_t>((size_t)nb * n2, n2);
                     if (nc > 1 && (size_t)nc * per * n * rank > tcap) { nc = 1; per = nb; }
                     if (nc * per > nb)
-                        HIPCHK(launch_fill(h->d_T + (long)nb * n * rank, (long)(nc * per - nb) * n * rank, 0.0, st));
+                        HIPCHK(launch_fill(h->d_T + (long)nb * n * rank, (long)(nc * per - nb) * n * rank, 0.0, ls));
                     {
-                        TimedLaunch tl(h, st, 31, nd * (nd + 1.0) * rank * nb);
-                        const int brc = blas_lowrank_stage2(h, st, n, rank, per, nc, h->d_F);
+                        TimedLaunch tl(h, ls, 31, nd * (nd + 1.0) * rank * nb);
+                        const int brc = blas_lowrank_stage2(h, ls, n, rank, per, nc, h->d_F);
                         if (brc) return brc;
                     }
-                    if (nc > 1) HIPCHK(launch_sum_partials(h->d_F, nc, n2, h->d_Kt, st));
+                    if (nc > 1) HIPCHK(launch_sum_partials(h->d_F, nc, n2, h->d_Kt, ls));
                 } else if (!use_lr) {
                     // dense form: T_b = F_b D, K += W_b T_b F_b on the upper tiles (F_b symmetric)
                     GemmArgs g1{};
@@ -644,8 +667,8 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
                     g1.C = h->d_T; g1.ldc = n; g1.sC = n2;
                     g1.nbatch = 2 * gc; g1.alpha = nullptr; g1.alpha0 = 1.0; g1.reduce = 0; g1.slices = 1;
                     {
-                        TimedLaunch tl(h, st, 0, 2.0 * nd * nd * nd * g1.nbatch);
-                        HIPCHK(launch_dgemm(g1, st));
+                        TimedLaunch tl(h, ls, 0, 2.0 * nd * nd * nd * g1.nbatch);
+                        HIPCHK(launch_dgemm(g1, ls));
                     }
                     for (int half = 0; half < 2; ++half) {
                         GemmArgs g2{};
@@ -655,22 +678,21 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
                         g2.C = h->d_Kt; g2.ldc = n; g2.sC = 0;
                         g2.nbatch = gc; g2.alpha = nullptr; g2.alpha0 = 1.0; g2.reduce = 1; g2.upper = 1;
                         g2.slices = std::max(1, std::min(gc, 2048 / std::max(1, upper_tiles)));
-                        TimedLaunch tl(h, st, 0, nd * (nd + 1.0) * nd * g2.nbatch);
-                        HIPCHK(launch_dgemm(g2, st));
+                        TimedLaunch tl(h, ls, 0, nd * (nd + 1.0) * nd * g2.nbatch);
+                        HIPCHK(launch_dgemm(g2, ls));
                     }
                 }
             }
         }
     }
-    HIPCHK(hipEventRecord(h->ev[2], st));
-
+    
     // B7: self term -(pi/(V w^2)) S_bra S_ket
     if (h->parts & PBC_JK_PART_SELF) {
         const double f = -kPi / (S.lat.V * S.omega * S.omega);
         if (wantJ) {
-            HIPCHK(launch_fill(h->d_scal, 1, 0.0, st));
-            HIPCHK(launch_dot(h->d_S, h->d_Dt, n2, h->d_scal, st));
-            HIPCHK(launch_axpy_scaled(h->d_Jt, h->d_S, n2, f, h->d_scal, st));
+            HIPCHK(launch_fill(h->d_scal, 1, 0.0, ls));
+            HIPCHK(launch_dot(h->d_S, h->d_Dt, n2, h->d_scal, ls));
+            HIPCHK(launch_axpy_scaled(h->d_Jt, h->d_S, n2, f, h->d_scal, ls));
         }
         if (wantK) {
             GemmArgs g1{};
@@ -681,17 +703,21 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
             g1.nbatch = 1; g1.alpha0 = 1.0; g1.reduce = 0; g1.slices = 1;
             const double nd = (double)n;
             {
-                TimedLaunch tg(h, st, 0, 2.0 * nd * nd * nd);
-                HIPCHK(launch_dgemm(g1, st));
+                TimedLaunch tg(h, ls, 0, 2.0 * nd * nd * nd);
+                HIPCHK(launch_dgemm(g1, ls));
             }
             GemmArgs g2 = g1;
             g2.A = h->d_T; g2.B = h->d_S; g2.C = h->d_Kt; g2.alpha0 = f; g2.reduce = 1; g2.upper = kt_full ? 0 : 1;
             {
-                TimedLaunch tg(h, st, 0, nd * (nd + 1.0) * nd);
-                HIPCHK(launch_dgemm(g2, st));
+                TimedLaunch tg(h, ls, 0, nd * (nd + 1.0) * nd);
+                HIPCHK(launch_dgemm(g2, ls));
             }
         }
     }
+    HIPCHK(hipEventRecord(h->ev[5], ls));
+    HIPCHK(hipEventRecord(h->ev_join, ls));
+    HIPCHK(hipStreamWaitEvent(st, h->ev_join, 0));
+    HIPCHK(hipEventRecord(h->ev[2], st));
 
     // B8: symmetrise, back-transform, energies
     if (wantJ) {
@@ -719,6 +745,15 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
         if (E_K) *E_K = -0.25 * e[1];
     }
     return 0;
+}
+
+// A build that fails part-way leaves no work of its own in flight on the
+// side stream.
+int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, double *E_K, hipStream_t st)
+{
+    const int rc = run_build_streams(h, dD, dJ, dK, E_J, E_K, st);
+    if (rc && h->side) (void)hipStreamSynchronize(h->side);
+    return rc;
 }
 
 bool finite_all(const double *p, size_t n)
@@ -801,6 +836,7 @@ void handle_drop_device(pbc_jk *h)
 {
     (void)hipSetDevice(h->device);
     if (h->own) (void)hipStreamSynchronize(h->own);
+    if (h->side) (void)hipStreamSynchronize(h->side);
     release_device(h);
 }
 
@@ -813,6 +849,7 @@ void handle_delete(pbc_jk *h)
     if (!h) return;
     (void)hipSetDevice(h->device);
     if (h->own) (void)hipStreamSynchronize(h->own);
+    if (h->side) (void)hipStreamSynchronize(h->side);
     release(h);
     delete h;
 }
@@ -932,7 +969,7 @@ int pbc_jk_stats(const pbc_jk *hc, pbc_jk_counters *out)
         HIPCHK(hipEventSynchronize(h->ev[3]));
         float a = 0, b = 0, c = 0;
         HIPCHK(hipEventElapsedTime(&a, h->ev[0], h->ev[1]));
-        HIPCHK(hipEventElapsedTime(&b, h->ev[1], h->ev[2]));
+        HIPCHK(hipEventElapsedTime(&b, h->ev[4], h->ev[5]));
         HIPCHK(hipEventElapsedTime(&c, h->ev[2], h->ev[3]));
         h->st.t_sr_ms = a; h->st.t_lr_ms = b; h->st.t_other_ms = c;
         unsigned long long cnt[kNumCounters];
