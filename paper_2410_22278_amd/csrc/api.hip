@@ -453,9 +453,12 @@ int blas_lowrank_stage1(pbc_jk *h, hipStream_t st, int n, int rank, int nb)
 
 // Split reduction of K = sum_b Y_b Y_b^T over nc chunks of `per` consecutive
 // Y_b (a chunk is one n x (per rank) column-major matrix with ld n, since the
-// Y_b sit one after another): chunk c gives Y_c Y_c^T.  One chunk is added
-// straight into K; otherwise chunk c's product goes to P + c n^2.
-int blas_lowrank_stage2(pbc_jk *h, hipStream_t st, int n, int rank, int per, int nc, double *P)
+// Y_b sit one after another): chunk c gives Y_c Y_c^T.  The product is
+// symmetric, so only three of its 2 x 2 blocks are formed (rows split at
+// bs = ceil(n/2)): the two diagonal blocks and the block of rows >= bs,
+// columns < bs, which read row-major is the upper block.  One chunk is added
+// straight into K; otherwise chunk c's blocks go to P + c n^2.
+int blas_lowrank_stage2(pbc_jk *h, hipStream_t st, int n, int rank, int nb, int per, int nc, double *P)
 {
     rocblas_handle bh = thread_blas();
     if (!bh) return fail(PBC_JK_EDEVICE, "rocblas_create_handle failed");
@@ -463,11 +466,19 @@ int blas_lowrank_stage2(pbc_jk *h, hipStream_t st, int n, int rank, int per, int
     const double one = 1.0, zero = 0.0;
     const long kc = (long)per * rank;
     double *C = nc == 1 ? h->d_Kt : P;
-    const rocblas_status rs = rocblas_dgemm_strided_batched(
-        bh, rocblas_operation_none, rocblas_operation_transpose, n, n, (rocblas_int)kc, &one, h->d_T, n,
-        (rocblas_stride)kc * n, h->d_T, n, (rocblas_stride)kc * n, nc == 1 ? &one : &zero, C, n,
-        (rocblas_stride)n * n, nc);
-    if (rs != rocblas_status_success) return fail(PBC_JK_EDEVICE, "rocblas_dgemm_strided_batched failed");
+    const int bs = (n + 1) / 2, n1 = n - bs;
+    const int blk[3][4] = {{0, 0, bs, bs}, {bs, 0, n1, bs}, {bs, bs, n1, n1}};   // row0, col0, rows, cols
+    for (const auto &b : blk) {
+        if (b[2] == 0 || b[3] == 0) continue;
+        // algorithmic FLOPs: a diagonal block counts its triangle
+        const double fl = (b[0] == b[1] ? (double)b[2] * (b[2] + 1.0) : 2.0 * b[2] * b[3]) * rank * nb;
+        TimedLaunch tl(h, st, 31, fl);
+        const rocblas_status rs = rocblas_dgemm_strided_batched(
+            bh, rocblas_operation_none, rocblas_operation_transpose, b[2], b[3], (rocblas_int)kc, &one,
+            h->d_T + b[0], n, (rocblas_stride)kc * n, h->d_T + b[1], n, (rocblas_stride)kc * n,
+            nc == 1 ? &one : &zero, C + b[0] + (long)b[1] * n, n, (rocblas_stride)n * n, nc);
+        if (rs != rocblas_status_success) return fail(PBC_JK_EDEVICE, "rocblas_dgemm_strided_batched failed");
+    }
     return 0;
 }
 
@@ -572,9 +583,7 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
 
     // B6 prelude (side stream, beside the short range): the density factor of
     // the low-rank exchange and its rank, read back to the host (one
-    // synchronisation, after the short range is queued).  Kt then holds full
-    // matrices (low-rank exchange) or only the upper output tiles of
-    // launch_dgemm (dense exchange, self term).
+    // synchronisation, after the short range is queued).
     const int nG = (int)S.Gw.size();
     const bool lr_on = (h->parts & PBC_JK_PART_LR) && nG > 0 && (wantJ || wantK);
     HIPCHK(hipEventRecord(h->ev[4], ls));
@@ -603,7 +612,8 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
     }
     const bool use_lr = lowrank && !h->h_ctl[1];
     const int rank = use_lr ? h->h_ctl[0] : 0;
-    const bool kt_full = use_lr;
+    // Kt read back by upper blocks: halves (low-rank form) or GEMM tiles
+    const int kt_block = use_lr ? (n + 1) / 2 : kGemmTile;
     if (lowrank && h->profile && h->last_rslot < h->ntimed) h->tflops[h->last_rslot] = 2.0 * (double)n * n * h->h_ctl[0];
 
 
@@ -653,11 +663,10 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
                     if (nc * per > nb)
                         HIPCHK(launch_fill(h->d_T + (long)nb * n * rank, (long)(nc * per - nb) * n * rank, 0.0, ls));
                     {
-                        TimedLaunch tl(h, ls, 31, nd * (nd + 1.0) * rank * nb);
-                        const int brc = blas_lowrank_stage2(h, ls, n, rank, per, nc, h->d_F);
+                        const int brc = blas_lowrank_stage2(h, ls, n, rank, nb, per, nc, h->d_F);
                         if (brc) return brc;
                     }
-                    if (nc > 1) HIPCHK(launch_sum_partials(h->d_F, nc, n2, h->d_Kt, ls));
+                    if (nc > 1) HIPCHK(launch_sum_partials(h->d_F, nc, n, (n + 1) / 2, h->d_Kt, ls));
                 } else if (!use_lr) {
                     // dense form: T_b = F_b D, K += W_b T_b F_b on the upper tiles (F_b symmetric)
                     GemmArgs g1{};
@@ -707,7 +716,7 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
                 HIPCHK(launch_dgemm(g1, ls));
             }
             GemmArgs g2 = g1;
-            g2.A = h->d_T; g2.B = h->d_S; g2.C = h->d_Kt; g2.alpha0 = f; g2.reduce = 1; g2.upper = kt_full ? 0 : 1;
+            g2.A = h->d_T; g2.B = h->d_S; g2.C = h->d_Kt; g2.alpha0 = f; g2.reduce = 1; g2.upper = use_lr ? 0 : 1;
             {
                 TimedLaunch tg(h, ls, 0, nd * (nd + 1.0) * nd);
                 HIPCHK(launch_dgemm(g2, ls));
@@ -725,7 +734,7 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
         HIPCHK(launch_final(fa, st));
     }
     if (wantK) {
-        FinalArgs fa{h->d_Y, h->d_Kt, n, nb, kt_full ? 0 : 1, h->d_inv_ci, h->d_inv_cc, Ko};
+        FinalArgs fa{h->d_Y, h->d_Kt, n, nb, kt_block, h->d_inv_ci, h->d_inv_cc, Ko};
         HIPCHK(launch_final(fa, st));
     }
     if (E_J || E_K) {

@@ -95,8 +95,9 @@ hipError_t launch_sfac(int cls, const SfacArgs &a, hipStream_t st);
 hipError_t launch_dot_batched(const double *F, const double *Dt, int n2, int nb, double *rho, hipStream_t st);
 
 // Jt[mu nu] += sum_g Gw[g] (F[g][mu nu] rho[g] + F[ng+g][mu nu] rho[ng+g]).
-// K[i] += sum_c P[c][i] for c < nc.
-hipError_t launch_sum_partials(const double *P, int nc, long n2, double *K, hipStream_t st);
+// K[r][c] += sum_k P[k][r][c] for k < nc (n x n matrices), skipping the block
+// r >= bs, c < bs.
+hipError_t launch_sum_partials(const double *P, int nc, int n, int bs, double *K, hipStream_t st);
 // Jt += sum_g Gw[g] (Re F_g rho_g + Im F_g rho'_g); Gw NULL: unit weights.
 hipError_t launch_jlr(const double *F, const double *rho, const double *Gw, int ng, int n2, double *Jt,
                       hipStream_t st);
@@ -168,7 +169,7 @@ hipError_t launch_axpy_scaled(double *Y, const double *X, long n, double f, cons
 struct FinalArgs {
     const double *X, *Jt;
     int nbfc, nbf;
-    int jt_upper;          // Jt holds only the upper output tiles of launch_dgemm
+    int jt_block;          // > 0: Jt holds only its upper blocks of this size (block row <= block column); 0: whole
     const int *inv_ci;     // 3 * nbf scaled-Cartesian indices (-1 = none)
     const double *inv_cc;  // 3 * nbf coefficients
     double *out;           // nbf^2

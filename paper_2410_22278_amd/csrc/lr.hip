@@ -179,10 +179,14 @@ __global__ __launch_bounds__(256) void k_jlr(const double *F, const double *rho,
     Jt[i] += s;
 }
 
-// K[i] += sum_c P[c][i], c < nc (partial products of the split reduction)
-__global__ __launch_bounds__(256) void k_sum_partials(const double *P, int nc, long n2, double *K)
+// K[r][c] += sum_k P[k][r][c], k < nc (partial products of the split
+// reduction), except in the block r >= bs, c < bs, which the partial
+// products do not form.
+__global__ __launch_bounds__(256) void k_sum_partials(const double *P, int nc, int n, int bs, double *K)
 {
+    const long n2 = (long)n * n;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += (long)gridDim.x * blockDim.x) {
+        if (i / n >= bs && i % n < bs) continue;
         double s = 0.0;
         for (int c = 0; c < nc; ++c) s += P[(long)c * n2 + i];
         K[i] += s;
@@ -259,7 +263,7 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs a)
             int j = a.inv_ci[3 * q + v];
             if (j < 0) continue;
             long jt = (long)i * nc + j;
-            if (a.jt_upper && i / kGemmTile > j / kGemmTile) jt = (long)j * nc + i;
+            if (a.jt_block > 0 && i / a.jt_block > j / a.jt_block) jt = (long)j * nc + i;
             double x = a.X[(long)i * nc + j] + a.X[(long)j * nc + i] + a.Jt[jt];
             s += a.inv_cc[3 * p + u] * a.inv_cc[3 * q + v] * x;
         }
@@ -712,11 +716,12 @@ hipError_t launch_dot_batched(const double *F, const double *Dt, int n2, int nb,
     return hipGetLastError();
 }
 
-hipError_t launch_sum_partials(const double *P, int nc, long n2, double *K, hipStream_t st)
+hipError_t launch_sum_partials(const double *P, int nc, int n, int bs, double *K, hipStream_t st)
 {
+    const long n2 = (long)n * n;
     if (nc <= 0 || n2 <= 0) return hipSuccess;
     const long blocks = std::min<long>(4096, (n2 + 255) / 256);
-    hipLaunchKernelGGL(k_sum_partials, dim3((unsigned)blocks), dim3(256), 0, st, P, nc, n2, K);
+    hipLaunchKernelGGL(k_sum_partials, dim3((unsigned)blocks), dim3(256), 0, st, P, nc, n, bs, K);
     return hipGetLastError();
 }
 
