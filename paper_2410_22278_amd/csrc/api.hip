@@ -456,8 +456,8 @@ int blas_lowrank_stage1(pbc_jk *h, hipStream_t st, int n, int rank, int nb)
 // Y_b sit one after another): chunk c gives Y_c Y_c^T.  The product is
 // symmetric, so only three of its 2 x 2 blocks are formed (rows split at
 // bs = ceil(n/2)): the two diagonal blocks and the block of rows >= bs,
-// columns < bs, which read row-major is the upper block.  One chunk is added
-// straight into K; otherwise chunk c's blocks go to P + c n^2.
+// columns < bs, which read row-major is the upper block.  Chunk c's blocks go
+// to P + c n^2 (added into K afterwards by launch_sum_partials).
 int blas_lowrank_stage2(pbc_jk *h, hipStream_t st, int n, int rank, int nb, int per, int nc, double *P)
 {
     rocblas_handle bh = thread_blas();
@@ -465,7 +465,7 @@ int blas_lowrank_stage2(pbc_jk *h, hipStream_t st, int n, int rank, int nb, int 
     if (rocblas_set_stream(bh, st) != rocblas_status_success) return fail(PBC_JK_EDEVICE, "rocblas_set_stream failed");
     const double one = 1.0, zero = 0.0;
     const long kc = (long)per * rank;
-    double *C = nc == 1 ? h->d_Kt : P;
+    double *C = P;
     const int bs = (n + 1) / 2, n1 = n - bs;
     const int blk[3][4] = {{0, 0, bs, bs}, {bs, 0, n1, bs}, {bs, bs, n1, n1}};   // row0, col0, rows, cols
     for (const auto &b : blk) {
@@ -476,7 +476,7 @@ int blas_lowrank_stage2(pbc_jk *h, hipStream_t st, int n, int rank, int nb, int 
         const rocblas_status rs = rocblas_dgemm_strided_batched(
             bh, rocblas_operation_none, rocblas_operation_transpose, b[2], b[3], (rocblas_int)kc, &one,
             h->d_T + b[0], n, (rocblas_stride)kc * n, h->d_T + b[1], n, (rocblas_stride)kc * n,
-            nc == 1 ? &one : &zero, C + b[0] + (long)b[1] * n, n, (rocblas_stride)n * n, nc);
+            &zero, C + b[0] + (long)b[1] * n, n, (rocblas_stride)n * n, nc);
         if (rs != rocblas_status_success) return fail(PBC_JK_EDEVICE, "rocblas_dgemm_strided_batched failed");
     }
     return 0;
@@ -653,7 +653,8 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
                     }
                     // chunks of `per` Y_b, enough of them to fill the device with
                     // output tiles; the last chunk is padded with zero Y_b when the
-                    // buffer has room, else everything goes into one product
+                    // buffer has room, else everything goes into one product.  The
+                    // chunk products go to the F buffer (free by now), then into K.
                     const long tiles = (long)((n + 127) / 128) * ((n + 127) / 128);
                     int nc = (int)std::max(1L, std::min<long>(nb, (kStage2Tiles + tiles - 1) / tiles));
                     int per = (nb + nc - 1) / nc;
@@ -666,7 +667,7 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
                         const int brc = blas_lowrank_stage2(h, ls, n, rank, nb, per, nc, h->d_F);
                         if (brc) return brc;
                     }
-                    if (nc > 1) HIPCHK(launch_sum_partials(h->d_F, nc, n, (n + 1) / 2, h->d_Kt, ls));
+                    HIPCHK(launch_sum_partials(h->d_F, nc, n, (n + 1) / 2, h->d_Kt, ls));
                 } else if (!use_lr) {
                     // dense form: T_b = F_b D, K += W_b T_b F_b on the upper tiles (F_b symmetric)
                     GemmArgs g1{};

@@ -5,8 +5,11 @@ a positive semidefinite density of low rank, through a device pivoted
 Cholesky factor D = L L^T as sum_G W_G (A_G L)(A_G L)^T + (B_G L)(B_G L)^T.
 The factor is accepted only after an entrywise check of D - L L^T, so both
 forms must agree with the oracle to the FP64 bar; the counters say which
-form ran.  The 144-AO cell spans two 128-wide output tiles, so the
-upper-tile-only accumulation and its symmetric read-back are exercised.
+form ran.  The 144-AO cell spans two 128-wide output tiles, so the dense
+form's upper-tile-only accumulation and its symmetric read-back are
+exercised; the low-rank form forms three of the four half blocks of each
+Y Y^T and reads K back by upper half blocks, which the 25-AO cell (odd, so
+the two halves differ in size) checks as well.
 """
 import numpy as np
 import pytest
@@ -17,6 +20,7 @@ pytestmark = pytest.mark.gpu
 
 CELL144 = dict(seed=41, natom=36, a_ang=7.0, recipe=((0, 0), (1, 0)), delta=1e-10, g_cut=2.0, r_cut=8.0)
 CELL_D = dict(seed=21, natom=2, recipe=((0, 0), (1, 0), (2, 1)), a_ang=3.2, lo=0.3, hi=4.0)
+CELL_ODD = dict(seed=7, natom=5, recipe=((0, 0), (0, 0), (1, 0)), a_ang=5.0, delta=1e-10, g_cut=2.0, r_cut=8.0)
 
 
 @pytest.fixture(scope="module")
@@ -57,6 +61,19 @@ def test_lr_forms_multi_tile(lib, oracle_mod, mode):
         assert st["lr_rank"] == s.nbf // 2      # D = C C^T with nbf/2 orbitals
     else:
         assert st["lr_rank"] == -1
+
+
+@pytest.mark.parametrize("mode", ["auto", "dense"])
+def test_lr_forms_odd_size(lib, oracle_mod, mode):
+    s = inputs.small_cell(**CELL_ODD)
+    assert s.nbf % 2 == 1
+    ref = oracle_mod.jk(s, parts="lr,self")
+    m = lib.LR_AUTO if mode == "auto" else lib.LR_DENSE
+    J, K, st = _lr(lib, s, s.D, m)
+    dJ, dK = _cmp(f"lr+self {mode} nbf={s.nbf} rank={st['lr_rank']:.0f}", J, K, ref)
+    assert dJ < 1e-9 and dK < 1e-9
+    assert np.abs(K - K.T).max() < 1e-13
+    assert (st["lr_rank"] > 0) if mode == "auto" else (st["lr_rank"] == -1)
 
 
 def test_lr_d_shells_scaled_basis(lib, oracle_mod):
