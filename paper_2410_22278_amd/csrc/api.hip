@@ -112,6 +112,10 @@ struct pbc_jk {
     // before the final assembly
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // the first reciprocal chunk's structure factors and J run on `side2`
+    // while `side` factorises the density
+    hipStream_t side2 = nullptr;
+    hipEvent_t ev_sf = nullptr;
     // event pairs around GEMM and structure-factor launches of one build
     static constexpr int kMaxTimed = 256;
     std::vector<hipEvent_t> tev;
@@ -212,6 +216,10 @@ void release(pbc_jk *h)
     h->own = nullptr;
     if (h->side) (void)hipStreamDestroy(h->side);
     h->side = nullptr;
+    if (h->side2) (void)hipStreamDestroy(h->side2);
+    h->side2 = nullptr;
+    if (h->ev_sf) (void)hipEventDestroy(h->ev_sf);
+    h->ev_sf = nullptr;
     if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
     if (h->ev_join) (void)hipEventDestroy(h->ev_join);
     h->ev_fork = h->ev_join = nullptr;
@@ -248,6 +256,8 @@ int create_device(pbc_jk *h)
         HIPCHK(hipGetDevice(&h->device));
         if (!h->own) HIPCHK(hipStreamCreateWithFlags(&h->own, hipStreamNonBlocking));
         if (!h->side) HIPCHK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+        if (!h->side2) HIPCHK(hipStreamCreateWithFlags(&h->side2, hipStreamNonBlocking));
+        if (!h->ev_sf) HIPCHK(hipEventCreateWithFlags(&h->ev_sf, hipEventDisableTiming));
         if (!h->ev_fork) HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
         if (!h->ev_join) HIPCHK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
         for (auto &e : h->ev)
@@ -587,6 +597,35 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
     const int nG = (int)S.Gw.size();
     const bool lr_on = (h->parts & PBC_JK_PART_LR) && nG > 0 && (wantJ || wantK);
     HIPCHK(hipEventRecord(h->ev[4], ls));
+    SfacArgs sa{};
+    sa.pairs = h->d_pairs; sa.sp_start = h->d_sp_start; sa.sp_pairs = h->d_sp_pairs;
+    sa.sp_shA = h->d_sp_shA; sa.sp_shB = h->d_sp_shB; sa.sh_l = h->d_sh_l; sa.sh_aoc = h->d_sh_aoc;
+    sa.F = h->d_F; sa.nbfc = n; sa.Gs = nullptr;
+    // structure factors of one chunk of reciprocal vectors into F, then their
+    // J contribution
+    auto sfac_j = [&](int g0, int gc, hipStream_t s) -> int {
+        HIPCHK(launch_fill(h->d_F, 2L * gc * n2, 0.0, s));
+        sa.G = h->d_G + 3 * g0; sa.Gs = h->d_Gs + g0; sa.ng = gc;
+        {
+            TimedLaunch tl(h, s, 1, 0.0);
+            for (int c = 0; c < kNumClass; ++c) {
+                sa.sp0 = S.sp_class_start[c];
+                sa.nsp = S.sp_class_start[c + 1] - S.sp_class_start[c];
+                HIPCHK(launch_sfac(c, sa, s));
+            }
+        }
+        if (wantJ) {
+            HIPCHK(launch_dot_batched(h->d_F, h->d_Dt, (int)n2, 2 * gc, h->d_rho, s));
+            HIPCHK(launch_jlr(h->d_F, h->d_rho, nullptr, gc, (int)n2, h->d_Jt, s));
+        }
+        return 0;
+    };
+    if (lr_on) {
+        HIPCHK(hipStreamWaitEvent(h->side2, h->ev_fork, 0));
+        const int frc = sfac_j(0, std::min(h->gchunk, nG), h->side2);
+        if (frc) return frc;
+        HIPCHK(hipEventRecord(h->ev_sf, h->side2));
+    }
     const bool lowrank = lr_on && wantK && h->lr_mode == PBC_JK_LR_AUTO;
     h->lr_ran = lowrank;
     if (lowrank) {
@@ -619,26 +658,14 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
 
     // B5/B6: reciprocal-space J and K (side stream)
     if (lr_on) {
-        SfacArgs sa{};
-        sa.pairs = h->d_pairs; sa.sp_start = h->d_sp_start; sa.sp_pairs = h->d_sp_pairs;
-        sa.sp_shA = h->d_sp_shA; sa.sp_shB = h->d_sp_shB; sa.sh_l = h->d_sh_l; sa.sh_aoc = h->d_sh_aoc;
-        sa.F = h->d_F; sa.nbfc = n; sa.Gs = nullptr;
         const int ntile = (n + kGemmTile - 1) / kGemmTile, upper_tiles = ntile * (ntile + 1) / 2;
         for (int g0 = 0; g0 < nG; g0 += h->gchunk) {
             const int gc = std::min(h->gchunk, nG - g0);
-            HIPCHK(launch_fill(h->d_F, 2L * gc * n2, 0.0, ls));
-            sa.G = h->d_G + 3 * g0; sa.Gs = h->d_Gs + g0; sa.ng = gc;
-            {
-                TimedLaunch tl(h, ls, 1, 0.0);
-                for (int c = 0; c < kNumClass; ++c) {
-                    sa.sp0 = S.sp_class_start[c];
-                    sa.nsp = S.sp_class_start[c + 1] - S.sp_class_start[c];
-                    HIPCHK(launch_sfac(c, sa, ls));
-                }
-            }
-            if (wantJ) {
-                HIPCHK(launch_dot_batched(h->d_F, h->d_Dt, (int)n2, 2 * gc, h->d_rho, ls));
-                HIPCHK(launch_jlr(h->d_F, h->d_rho, nullptr, gc, (int)n2, h->d_Jt, ls));
+            if (g0 == 0) {
+                HIPCHK(hipStreamWaitEvent(ls, h->ev_sf, 0));   // chunk 0 ran on side2
+            } else {
+                const int frc = sfac_j(g0, gc, ls);
+                if (frc) return frc;
             }
             if (wantK) {
                 const double nd = (double)n;
@@ -763,6 +790,7 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
 {
     const int rc = run_build_streams(h, dD, dJ, dK, E_J, E_K, st);
     if (rc && h->side) (void)hipStreamSynchronize(h->side);
+    if (rc && h->side2) (void)hipStreamSynchronize(h->side2);
     return rc;
 }
 
@@ -847,6 +875,7 @@ void handle_drop_device(pbc_jk *h)
     (void)hipSetDevice(h->device);
     if (h->own) (void)hipStreamSynchronize(h->own);
     if (h->side) (void)hipStreamSynchronize(h->side);
+    if (h->side2) (void)hipStreamSynchronize(h->side2);
     release_device(h);
 }
 
@@ -860,6 +889,7 @@ void handle_delete(pbc_jk *h)
     (void)hipSetDevice(h->device);
     if (h->own) (void)hipStreamSynchronize(h->own);
     if (h->side) (void)hipStreamSynchronize(h->side);
+    if (h->side2) (void)hipStreamSynchronize(h->side2);
     release(h);
     delete h;
 }
