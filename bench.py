@@ -199,8 +199,8 @@ def main():
                     help="only copy a MIB-sized float64 buffer 3 times on the GPU (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs the hot path on one GPU only; --gpus above 1 is not "
-              "supported (the multi-GPU sharding is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py: the J/K build runs on one GPU; --gpus above 1 is not supported "
+              "(no multi-GPU path is implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
