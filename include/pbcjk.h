@@ -171,7 +171,12 @@ int pbc_jk_build(pbc_jk *h, const double *D, double *J, double *K, double *E_J, 
 
 /* One build on device memory: dD, dJ, dK are device pointers (nbf x nbf);
  * dJ or dK may be NULL to skip.  Work is queued on `stream` (a hipStream_t,
- * NULL = the default stream).  E_J/E_K are host pointers (may be NULL); when
+ * NULL = the default stream): the reciprocal part runs on streams of the
+ * handle that start after the work already queued on `stream` and that
+ * `stream` waits for before the final assembly, so the build is ordered on
+ * `stream` like a single launch.  With the low-rank exchange the call
+ * waits on the host for the density factor's rank (one synchronisation of
+ * the handle's own stream).  E_J/E_K are host pointers (may be NULL); when
  * given, the call waits for the stream before returning.  D is not checked
  * for symmetry on this path. */
 int pbc_jk_build_device(pbc_jk *h, const double *dD, double *dJ, double *dK,
