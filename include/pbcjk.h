@@ -94,8 +94,11 @@ typedef struct {
  *                     > ewald_K;
  *   schwarz         : a primitive quartet is kept iff
  *                     Q_bra Q_ket max|D over the six shell-pair blocks it
- *                     couples| > schwarz, Q = the local-pair
- *                     Cauchy-Schwarz value of Sec. 2.4;
+ *                     couples| > schwarz, Q = the square root of the
+ *                     largest component of the primitive pair's own
+ *                     short-range integral (ab|ab) with the erfc(w r)/r
+ *                     kernel (the Cauchy-Schwarz bound of Sec. 2.4, eq.
+ *                     local_cauchy_schwarz_bound, for the real-space terms);
  *   fp32_below      : 0 = all quartets in FP64; otherwise quartets whose
  *                     density-weighted bound is below it run in FP32
  *                     (Sec. 3.5), accumulation stays FP64;
@@ -140,15 +143,16 @@ typedef struct {
                             exchange, or -1 when the dense form was used                */
     double t_chol_ms;    /* last build: duration of the density factorisation and of its
                             residual check                                                     */
-    int gemm_kernel;     /* kernel of t_gemm_ms: 0 k_dgemm<0> (dense exchange and self term),
-                            2 rocBLAS strided-batched products of the low-rank accumulation
-                            K += sum_G Y_G Y_G^T (Y_G = sqrt(W_G) F_G L), FLOPs counted on the
-                            upper triangle; 1 is no longer produced                            */
+    int gemm_kernel;     /* kernel of t_gemm_ms: 0 k_dgemm<0> (dense exchange T_G = F_G D,
+                            K += T_G F_G, and the self term), 3 k_dgemm<3> (low-rank
+                            accumulation K += sum_G Y_G Y_G^T, Y_G = sqrt(W_G) F_G L, FLOPs
+                            counted on the upper triangle)                                     */
     double t_sr_class_ms[21]; /* last build: duration of the short-range launches per class
                             pair (same order as terms_class)                                   */
-    double t_blas_ms;    /* last build: duration of the rocBLAS products Y = F L (low rank)    */
-    double blas_flops;   /* last build: their FLOPs (2 n^2 rank per F matrix)                  */
-    int n_blas;          /* last build: number of those rocBLAS calls                          */
+    double t_y_ms;       /* last build: duration of the low-rank products Y_G^T = L^T F_G
+                            (k_dgemm<2>)                                                       */
+    double y_flops;      /* last build: their FLOPs (2 n^2 rank per F matrix)                  */
+    int n_y;             /* last build: number of those launches                               */
     int sr_fold_mask;    /* last build: bit k set when class pair k summed its lattice shifts
                             before the transforms                                              */
     int sr_kernel_mask;  /* last build: bit k set when class pair k ran one wavefront per group
@@ -174,11 +178,11 @@ int pbc_jk_build(pbc_jk *h, const double *D, double *J, double *K, double *E_J, 
  * NULL = the default stream): the reciprocal part runs on streams of the
  * handle that start after the work already queued on `stream` and that
  * `stream` waits for before the final assembly, so the build is ordered on
- * `stream` like a single launch.  With the low-rank exchange the call
- * waits on the host for the density factor's rank (one synchronisation of
- * the handle's own stream).  E_J/E_K are host pointers (may be NULL); when
- * given, the call waits for the stream before returning.  D is not checked
- * for symmetry on this path. */
+ * `stream` like a single launch.  Nothing in the build waits on the host:
+ * the density factor's rank and the choice of exchange form stay on the
+ * device.  E_J/E_K are host pointers (may be NULL); when given, the call
+ * synchronises `stream` once at the end to read them, otherwise it returns
+ * with the build queued.  D is not checked for symmetry on this path. */
 int pbc_jk_build_device(pbc_jk *h, const double *dD, double *dJ, double *dK,
                         double *E_J, double *E_K, void *stream);
 
@@ -213,9 +217,12 @@ int pbc_jk_set_sr_classes(pbc_jk *h, int mask21);
  *                   with Y = A_G L and B_G L; the factor is accepted only if
  *                   max |D - L L^T| <= 2 tol max diag(D) + 4 n eps max diag(D)
  *                   and its rank is at most 3/4 of the Cartesian AO count,
- *                   otherwise the dense form runs.  The build reads the
- *                   factor's rank back once (the stream is synchronised
- *                   there).
+ *                   otherwise the dense form runs.  Both forms are queued
+ *                   and gated on the device by that decision, so the host
+ *                   never waits for it; the columns queued for the factor
+ *                   are the last finished build's rank plus 64 (the limit
+ *                   when unknown), and a factor needing more falls back to
+ *                   the dense form for that build.
  *   PBC_JK_LR_DENSE always the dense form T_G = A_G D, K_LR += W_G T_G A_G.
  * tol <= 0 keeps the current tolerance (default 1e-13).  EINVAL for an
  * unknown mode or a NULL handle. */

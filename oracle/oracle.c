@@ -18,6 +18,8 @@
  *   - periodic ERI (real + reciprocal + self)      Sec. 2.4, eq. pbc_eri_general_final
  *   - local-pair cutoffs                           Sec. 2.4, eqs. pbc_eri_pair_cutoff_*,
  *                                                   pbc_eri_cauchy_schwarz_cutoff_*
+ *   - quartet screen: short-range Cauchy-Schwarz   Sec. 2.4, eq. local_cauchy_schwarz_bound
+ *     factors from the pairs' own (ab|ab)_SR
  *   - real-space Ewald sphere per quartet          Sec. 2.4, eq. pbc_eri_real_cutoff_*
  *   - J and K at the Gamma point                   Sec. 2.5-2.6
  *   - point-charge Ewald energy (test utility)     Sec. 2.8, eq. nuclear_repulsion_energy
@@ -30,9 +32,9 @@
  * matrix products; the self term needs only the Gamma overlap.
  *
  * Readings of the paper that this file adopts (the paper is silent, garbled
- * or inconsistent there) are listed in the design doc and repeated at the point of
- * use: the pair-R bound prefactor, the constant C per primitive, the
- * density-weighted quartet screen and the global G sphere.
+ * or inconsistent there) are stated at the point of use: the pair-R bound
+ * prefactor, the constant C per primitive, the density-weighted quartet
+ * screen and the global G sphere.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -218,6 +220,39 @@ static void kernel_R000(int kind, int L, double rho, double omega, double T, dou
 /* molecular primitive integrals (test entry points)                       */
 /* ---------------------------------------------------------------------- */
 
+/* One element of a primitive quartet block for monomial Gaussians (Sec. 2.4
+ * McMurchie-Davidson form): components ca, cb (bra) and cc, cd (ket) given
+ * as exponent triples, Eab/Ecd the three axes of Hermite coefficients with
+ * tables of width la+lb+1 and lc+ld+1, R the Hermite integrals in an
+ * (L+1)^3 array.  Without the 2 pi^{5/2}/(pq sqrt(p+q)) prefactor. */
+static double quartet_elem(int lb, int ld, int ntab, int ntcd, const int ca[3], const int cb[3],
+                           const int cc[3], const int cd[3], const double *Eab[3], const double *Ecd[3],
+                           const double *R, int n1)
+{
+    const double *ex = Eab[0] + (ca[0] * (lb + 1) + cb[0]) * ntab;
+    const double *ey = Eab[1] + (ca[1] * (lb + 1) + cb[1]) * ntab;
+    const double *ez = Eab[2] + (ca[2] * (lb + 1) + cb[2]) * ntab;
+    const double *fx = Ecd[0] + (cc[0] * (ld + 1) + cd[0]) * ntcd;
+    const double *fy = Ecd[1] + (cc[1] * (ld + 1) + cd[1]) * ntcd;
+    const double *fz = Ecd[2] + (cc[2] * (ld + 1) + cd[2]) * ntcd;
+    double sum = 0.0;
+    for (int t = 0; t <= ca[0] + cb[0]; ++t)
+    for (int u = 0; u <= ca[1] + cb[1]; ++u)
+    for (int v = 0; v <= ca[2] + cb[2]; ++v) {
+        double eab = ex[t] * ey[u] * ez[v];
+        if (eab == 0.0) continue;
+        double inner = 0.0;
+        for (int tt = 0; tt <= cc[0] + cd[0]; ++tt)
+        for (int uu = 0; uu <= cc[1] + cd[1]; ++uu)
+        for (int vv = 0; vv <= cc[2] + cd[2]; ++vv) {
+            double s = ((tt + uu + vv) & 1) ? -1.0 : 1.0;
+            inner += s * fx[tt] * fy[uu] * fz[vv] * R[((t + tt) * n1 + (u + uu)) * n1 + (v + vv)];
+        }
+        sum += eab * inner;
+    }
+    return sum;
+}
+
 /* Cartesian block of one primitive quartet for monomial (not normalised)
  * Gaussians, any kernel (Sec. 2.4 McMurchie-Davidson form):
  *   (ab|cd) = 2 pi^{5/2}/(pq sqrt(p+q)) sum_t E^{ab}_t sum_s (-1)^{|s|} E^{cd}_s R_{t+s}(P-Q)
@@ -240,37 +275,45 @@ static void quartet_block(int la, int lb, int lc, int ld,
         int ca[3]; cart_comp(la, ia, ca);
         for (int ib = 0; ib < nb; ++ib) {
             int cb[3]; cart_comp(lb, ib, cb);
-            const double *ex = Eab[0] + (ca[0] * (lb + 1) + cb[0]) * ntab;
-            const double *ey = Eab[1] + (ca[1] * (lb + 1) + cb[1]) * ntab;
-            const double *ez = Eab[2] + (ca[2] * (lb + 1) + cb[2]) * ntab;
             for (int ic = 0; ic < nc; ++ic) {
                 int cc[3]; cart_comp(lc, ic, cc);
                 for (int id = 0; id < nd; ++id) {
                     int cd[3]; cart_comp(ld, id, cd);
-                    const double *fx = Ecd[0] + (cc[0] * (ld + 1) + cd[0]) * ntcd;
-                    const double *fy = Ecd[1] + (cc[1] * (ld + 1) + cd[1]) * ntcd;
-                    const double *fz = Ecd[2] + (cc[2] * (ld + 1) + cd[2]) * ntcd;
-                    double sum = 0.0;
-                    for (int t = 0; t <= ca[0] + cb[0]; ++t)
-                    for (int u = 0; u <= ca[1] + cb[1]; ++u)
-                    for (int v = 0; v <= ca[2] + cb[2]; ++v) {
-                        double eab = ex[t] * ey[u] * ez[v];
-                        if (eab == 0.0) continue;
-                        double inner = 0.0;
-                        for (int tt = 0; tt <= cc[0] + cd[0]; ++tt)
-                        for (int uu = 0; uu <= cc[1] + cd[1]; ++uu)
-                        for (int vv = 0; vv <= cc[2] + cd[2]; ++vv) {
-                            double s = ((tt + uu + vv) & 1) ? -1.0 : 1.0;
-                            inner += s * fx[tt] * fy[uu] * fz[vv]
-                                     * R[((t + tt) * n1 + (u + uu)) * n1 + (v + vv)];
-                        }
-                        sum += eab * inner;
-                    }
-                    out[((ia * nb + ib) * nc + ic) * nd + id] = pref * sum;
+                    out[((ia * nb + ib) * nc + ic) * nd + id] =
+                        pref * quartet_elem(lb, ld, ntab, ntcd, ca, cb, cc, cd, Eab, Ecd, R, n1);
                 }
             }
         }
     }
+}
+
+/* Largest diagonal element (ab|ab), over the Cartesian components ab, of the
+ * short-range (erfc) self-integral of one primitive pair whose components
+ * carry the normalisations Na, Nb (the pair's E tables include its Gaussian
+ * factor).  Its square root bounds every short-range integral of the pair
+ * by the Cauchy-Schwarz inequality (Sec. 2.4, eq. local_cauchy_schwarz_bound;
+ * the erfc kernel is positive definite). */
+static double sr_self_max(int la, int lb, double p, const double *Eab[3], const double *Na, const double *Nb,
+                          double omega)
+{
+    int L = 2 * (la + lb), n1 = L + 1;
+    double R000[ORC_MAXLQ + 1], zero[3] = {0.0, 0.0, 0.0};
+    kernel_R000(KER_SR, L, 0.5 * p, omega, 0.0, R000);
+    double *R = (double *)malloc(sizeof(double) * n1 * n1 * n1);
+    hermite_R(L, R000, zero, R);
+    double pref = 2.0 * pow(ORC_PI, 2.5) / (p * p * sqrt(2.0 * p));
+    double best = 0.0;
+    for (int ia = 0; ia < ncart(la); ++ia) {
+        int ca[3]; cart_comp(la, ia, ca);
+        for (int ib = 0; ib < ncart(lb); ++ib) {
+            int cb[3]; cart_comp(lb, ib, cb);
+            double v = pref * quartet_elem(lb, lb, la + lb + 1, la + lb + 1, ca, cb, ca, cb, Eab, Eab, R, n1);
+            v *= Na[ia] * Na[ia] * Nb[ib] * Nb[ib];
+            if (v > best) best = v;
+        }
+    }
+    free(R);
+    return best;
 }
 
 /* E tables of one primitive pair (three axes) for centres A, B. */
@@ -428,7 +471,7 @@ typedef struct {
     double ca, cb;               /* contraction coefficients                 */
     double Ca, Cb;               /* bound constants                          */
     double Kab;                  /* exp(-ab/p |A - B(R2)|^2)                 */
-    double Q;                    /* Cauchy-Schwarz value of the local pair    */
+    double Q;                    /* short-range Cauchy-Schwarz factor (quartet screen) */
     double *E;                   /* 3 axes of Hermite coefficients            */
     int n2[3];                   /* lattice index of the image offset         */
     double Na[ORC_MAXNC], Nb[ORC_MAXNC];  /* component normalisations         */
@@ -485,7 +528,6 @@ static void pair_cb(const double R[3], const int n[3], void *u_)
         P->Ca = bound_const(P->a, A->l, P->ca);
         P->Cb = bound_const(P->b, B->l, P->cb);
         P->Kab = g;
-        P->Q = u->Y0 * g;
         for (int x = 0; x < 3; ++x) P->n2[x] = n[x];
     }
     u->n++;
@@ -581,6 +623,15 @@ static int ctx_build(const orc_sys *in, ctx_t *X)
         P->S0 = P->ca * P->cb * pow(ORC_PI / P->p, 1.5);
         for (int x = 0; x < 3; ++x) P->P[x] = Pc[x];
         eo += 3 * (P->la + 1) * (P->lb + 1) * (P->la + P->lb + 1);
+    }
+    /* short-range Cauchy-Schwarz factor of every pair, for the quartet screen:
+     * sqrt of the largest normalised diagonal element (ab|ab)_SR */
+#pragma omp parallel for schedule(dynamic, 64)
+    for (long i = 0; i < X->npair; ++i) {
+        pair_t *P = &X->pair[i];
+        int sz = (P->la + 1) * (P->lb + 1) * (P->la + P->lb + 1);
+        const double *e[3] = {P->E, P->E + sz, P->E + 2 * sz};
+        P->Q = fabs(P->ca * P->cb) * sqrt(sr_self_max(P->la, P->lb, P->p, e, P->Na, P->Nb, in->omega));
     }
     return 0;
 }

@@ -1,6 +1,5 @@
 // C ABI of the periodic J/K library (see include/pbcjk.h).
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <chrono>
@@ -36,7 +35,7 @@ bool sr_per_lane(int cb, int ck)
 }
 constexpr double kFoldRmin = 20.0;   // bohr: cells with a shorter lattice vector start folded
 constexpr double kFoldRatio = 1.1;   // shifts per quartet above which the lattice sum is folded
-constexpr long kStage2Tiles = 8192;  // 128 x 128 output tiles aimed at by the split exchange reduction
+constexpr long kStage2Blocks = 4096; // workgroups aimed at by the split exchange accumulation
 constexpr double kCoopRatio = 4.5;   // shifts per quartet above which large d pairs use one
                                      // wavefront per group pair (it evaluates each shift once)
 
@@ -87,8 +86,10 @@ struct pbc_jk {
     // low-rank reciprocal exchange: density factor (by columns), work, control
     double *d_L = nullptr, *d_pw = nullptr;
     int *d_pwi = nullptr, *d_ctl = nullptr;
-    int *h_ctl = nullptr;        // pinned copy of the control block
-    int last_rslot = 0;          // timed-launch slot of the residual check
+    int *h_ctl = nullptr;        // pinned copy of the control block of the last finished factor
+    hipEvent_t ev_ctl = nullptr; // recorded after that copy
+    int lr_cap = 0;              // columns queued for the last factor (upper bound of its rank)
+    int y_tile = 64;             // output tile of the products Y_b^T = L^T F_b
     int lr_rmax = 0;
     bool lr_ran = false;
     size_t nbr_bytes_needed = 0;   // set once the neighbour lists are counted
@@ -117,12 +118,13 @@ struct pbc_jk {
     hipStream_t side2 = nullptr;
     hipEvent_t ev_sf = nullptr;
     // event pairs around GEMM and structure-factor launches of one build
-    static constexpr int kMaxTimed = 256;
+    static constexpr int kMaxTimed = 4096;
     std::vector<hipEvent_t> tev;
-    // 0 = plain GEMM (k_dgemm<0>), 1 = structure factors, 2 = low-rank
-    // accumulation and its residual check (k_dgemm<1>), 4 = factorisation,
-    // 5 + slot = the short-range launch of class pair `slot` (5..25),
-    // 30 = the rocBLAS products Y = F L
+    // 0 = plain GEMM (k_dgemm<0>), 1 = structure factors, 2 = residual check
+    // of the density factor (k_dgemm<1>), 4 = factorisation, 5 + slot = the
+    // short-range launch of class pair `slot` (5..25), 30 = Y_b^T = L^T F_b
+    // (k_dgemm<2>), 31 = K += sum_b Y_b Y_b^T (k_dgemm<3>); for 30 and 31 the
+    // recorded FLOPs are per unit of the density rank
     std::vector<int> tkind;
     std::vector<double> tflops;
     int ntimed = 0;
@@ -208,6 +210,8 @@ void release(pbc_jk *h)
         if (e) (void)hipEventDestroy(e);
     if (h->ev_cnt) (void)hipEventDestroy(h->ev_cnt);
     h->ev_cnt = nullptr;
+    if (h->ev_ctl) (void)hipEventDestroy(h->ev_ctl);
+    h->ev_ctl = nullptr;
     if (h->h_cnt) (void)hipHostFree(h->h_cnt);
     h->h_cnt = nullptr;
     if (h->h_ctl) (void)hipHostFree(h->h_ctl);
@@ -327,10 +331,12 @@ int create_device(pbc_jk *h)
         std::memset(h->h_ctl, 0, 4 * sizeof(int));
         std::memset(h->h_cnt, 0, kNumCounters * sizeof(unsigned long long));
         if (!h->ev_cnt) HIPCHK(hipEventCreateWithFlags(&h->ev_cnt, hipEventDisableTiming));
+        if (!h->ev_ctl) HIPCHK(hipEventCreateWithFlags(&h->ev_ctl, hipEventDisableTiming));
         // first guess: quartets of small cells have several lattice shifts
         for (bool &f : h->fold) f = S.lat.Rmin < kFoldRmin;
     }
     // reciprocal-space chunk: F and T hold 2 * gchunk matrices each
+    if (const char *e = std::getenv("PBCJK_Y_TILE")) h->y_tile = std::atoi(e) == 128 ? 128 : 64;
     const int nG = (int)S.Gw.size();
     double budget_mb = h->lr_budget_mb > 0 ? h->lr_budget_mb : 16384.0;
     if (const char *e = std::getenv("PBCJK_LR_BUDGET_MB")) budget_mb = std::max(64.0, std::atof(e));
@@ -430,68 +436,6 @@ int build_neighbours(pbc_jk *h)
     return 0;
 }
 
-// One rocBLAS handle per host thread (rocBLAS handles are not shared between
-// threads), created on first use and kept for the thread's lifetime.
-rocblas_handle thread_blas()
-{
-    struct Holder {
-        rocblas_handle h = nullptr;
-        ~Holder()
-        {
-            if (h) (void)rocblas_destroy_handle(h);
-        }
-    };
-    thread_local Holder holder;
-    if (!holder.h && rocblas_create_handle(&holder.h) != rocblas_status_success) holder.h = nullptr;
-    return holder.h;
-}
-
-// Y_b = F_b L for b < nb (column-major: F_b n x n, L n x rank with ld n,
-// Y_b n x rank with ld n, stored one after another in d_T).
-int blas_lowrank_stage1(pbc_jk *h, hipStream_t st, int n, int rank, int nb)
-{
-    rocblas_handle bh = thread_blas();
-    if (!bh) return fail(PBC_JK_EDEVICE, "rocblas_create_handle failed");
-    if (rocblas_set_stream(bh, st) != rocblas_status_success) return fail(PBC_JK_EDEVICE, "rocblas_set_stream failed");
-    const double one = 1.0, zero = 0.0;
-    const rocblas_status rs = rocblas_dgemm_strided_batched(
-        bh, rocblas_operation_none, rocblas_operation_none, n, rank, n, &one, h->d_F, n, (rocblas_stride)n * n,
-        h->d_L, n, 0, &zero, h->d_T, n, (rocblas_stride)n * rank, nb);
-    if (rs != rocblas_status_success) return fail(PBC_JK_EDEVICE, "rocblas_dgemm_strided_batched failed");
-    return 0;
-}
-
-// Split reduction of K = sum_b Y_b Y_b^T over nc chunks of `per` consecutive
-// Y_b (a chunk is one n x (per rank) column-major matrix with ld n, since the
-// Y_b sit one after another): chunk c gives Y_c Y_c^T.  The product is
-// symmetric, so only three of its 2 x 2 blocks are formed (rows split at
-// bs = ceil(n/2)): the two diagonal blocks and the block of rows >= bs,
-// columns < bs, which read row-major is the upper block.  Chunk c's blocks go
-// to P + c n^2 (added into K afterwards by launch_sum_partials).
-int blas_lowrank_stage2(pbc_jk *h, hipStream_t st, int n, int rank, int nb, int per, int nc, double *P)
-{
-    rocblas_handle bh = thread_blas();
-    if (!bh) return fail(PBC_JK_EDEVICE, "rocblas_create_handle failed");
-    if (rocblas_set_stream(bh, st) != rocblas_status_success) return fail(PBC_JK_EDEVICE, "rocblas_set_stream failed");
-    const double one = 1.0, zero = 0.0;
-    const long kc = (long)per * rank;
-    double *C = P;
-    const int bs = (n + 1) / 2, n1 = n - bs;
-    const int blk[3][4] = {{0, 0, bs, bs}, {bs, 0, n1, bs}, {bs, bs, n1, n1}};   // row0, col0, rows, cols
-    for (const auto &b : blk) {
-        if (b[2] == 0 || b[3] == 0) continue;
-        // algorithmic FLOPs: a diagonal block counts its triangle
-        const double fl = (b[0] == b[1] ? (double)b[2] * (b[2] + 1.0) : 2.0 * b[2] * b[3]) * rank * nb;
-        TimedLaunch tl(h, st, 31, fl);
-        const rocblas_status rs = rocblas_dgemm_strided_batched(
-            bh, rocblas_operation_none, rocblas_operation_transpose, b[2], b[3], (rocblas_int)kc, &one,
-            h->d_T + b[0], n, (rocblas_stride)kc * n, h->d_T + b[1], n, (rocblas_stride)kc * n,
-            &zero, C + b[0] + (long)b[1] * n, n, (rocblas_stride)n * n, nc);
-        if (rs != rocblas_status_success) return fail(PBC_JK_EDEVICE, "rocblas_dgemm_strided_batched failed");
-    }
-    return 0;
-}
-
 int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, double *E_K, hipStream_t st)
 {
     Setup &S = h->S;
@@ -575,7 +519,9 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
                     a.nbr_bra = !split ? pa.bra : prec ? pa.b32 : pa.b64;
                     a.nbr_ket = !split ? pa.ket : prec ? pa.k32 : pa.k64;
                     a.count = !split ? h->d_ncnt + slot : h->d_wcnt + 2 * slot + prec;
-                    // the FP32 list always sums its shifts in FP64 before the transforms
+                    // both lists follow the class pair's fold choice: folded, the shifts'
+                    // Hermite integrals are summed in FP64 before the transforms; unfolded,
+                    // each shift is transformed in the list's precision and added in FP64
                     TimedLaunch tl(h, st, 5 + slot, 0.0);
                     if (h->fold[slot]) h->st.sr_fold_mask |= 1 << slot;
                     if (coop && (h->coop_d[slot] || !sr_sliceable(cb, ck))) h->st.sr_kernel_mask |= 1 << slot;
@@ -592,8 +538,7 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
     HIPCHK(hipEventRecord(h->ev[1], st));
 
     // B6 prelude (side stream, beside the short range): the density factor of
-    // the low-rank exchange and its rank, read back to the host (one
-    // synchronisation, after the short range is queued).
+    // the low-rank exchange, whose rank stays on the device.
     const int nG = (int)S.Gw.size();
     const bool lr_on = (h->parts & PBC_JK_PART_LR) && nG > 0 && (wantJ || wantK);
     HIPCHK(hipEventRecord(h->ev[4], ls));
@@ -628,35 +573,44 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
     }
     const bool lowrank = lr_on && wantK && h->lr_mode == PBC_JK_LR_AUTO;
     h->lr_ran = lowrank;
+    // Columns queued for the density factor: the rank of the last finished
+    // factor plus a margin when it is known without waiting, else the limit.
+    // A factor that needs more columns than queued does not converge and the
+    // dense form runs instead (decided on the device); the next build then
+    // queues the limit again.
+    int cap = h->lr_rmax;
+    if (lowrank && h->ev_ctl && hipEventQuery(h->ev_ctl) == hipSuccess && h->h_ctl[2] && !h->h_ctl[1] &&
+        h->h_ctl[0] > 0)
+        cap = std::min(h->lr_rmax, ((h->h_ctl[0] + 64 + 63) / 64) * 64);
     if (lowrank) {
-        // D~ = L L^T on the device; R = L L^T into T, then the entrywise check
-        TimedLaunch tl(h, ls, 4, 0.0);
-        HIPCHK(launch_pchol(h->d_Dt, n, h->lr_tol, h->lr_rmax, h->d_L, h->d_pw, h->d_pwi, h->d_ctl, h->h_ctl, ls));
+        // D~ = L L^T on the device; R = L L^T into T, then the entrywise check.
+        // The rank and the choice of form stay in the control block: every
+        // product below reads them there, so nothing waits on the host.
+        {
+            TimedLaunch tl(h, ls, 4, 0.0);
+            HIPCHK(launch_pchol(h->d_Dt, n, h->lr_tol, cap, h->d_L, h->d_pw, h->d_pwi, h->d_ctl, ls));
+        }
         GemmArgs gr{};
-        gr.M = gr.N = n; gr.K = h->lr_rmax;
+        gr.M = gr.N = n; gr.K = cap;
         gr.A = h->d_L; gr.lda = n; gr.sA = 0; gr.transA = 1;
         gr.B = h->d_L; gr.ldb = n; gr.sB = 0;
         gr.C = h->d_T; gr.ldc = n; gr.sC = 0;
         gr.nbatch = 1; gr.alpha0 = 1.0; gr.slices = 1;
-        gr.ctl = h->d_ctl; gr.ctl_mode = 2;
-        h->last_rslot = h->ntimed;
+        gr.ctl = h->d_ctl; gr.ctl_mode = 2; gr.role = 1;
         {
-            TimedLaunch tg(h, ls, 2, 0.0);
+            TimedLaunch tg(h, ls, 2, 2.0 * (double)n * n);   // per unit of rank
             HIPCHK(launch_dgemm(gr, ls));
         }
         HIPCHK(launch_lowrank_check(h->d_Dt, h->d_T, n, h->d_pw, h->d_ctl, ls));
-        // the factor's rank sizes the products below: read it back
+        // a copy of the decision for the next build's column count and for the counters
         HIPCHK(hipMemcpyAsync(h->h_ctl, h->d_ctl, 4 * sizeof(int), hipMemcpyDeviceToHost, ls));
-        HIPCHK(hipStreamSynchronize(ls));
+        HIPCHK(hipEventRecord(h->ev_ctl, ls));
     }
-    const bool use_lr = lowrank && !h->h_ctl[1];
-    const int rank = use_lr ? h->h_ctl[0] : 0;
-    // Kt read back by upper blocks: halves (low-rank form) or GEMM tiles
-    const int kt_block = use_lr ? (n + 1) / 2 : kGemmTile;
-    if (lowrank && h->profile && h->last_rslot < h->ntimed) h->tflops[h->last_rslot] = 2.0 * (double)n * n * h->h_ctl[0];
+    h->lr_cap = cap;
 
-
-    // B5/B6: reciprocal-space J and K (side stream)
+    // B5/B6: reciprocal-space J and K (side stream).  Both exchange forms
+    // write the upper 128 x 128 tiles of K; with the low-rank form queued the
+    // dense products are gated on its failure (and the other way round).
     if (lr_on) {
         const int ntile = (n + kGemmTile - 1) / kGemmTile, upper_tiles = ntile * (ntile + 1) / 2;
         for (int g0 = 0; g0 < nG; g0 += h->gchunk) {
@@ -667,58 +621,62 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
                 const int frc = sfac_j(g0, gc, ls);
                 if (frc) return frc;
             }
-            if (wantK) {
-                const double nd = (double)n;
-                if (use_lr && rank > 0) {
-                    // F_b carries sqrt(W_b), so K += sum_b Y_b Y_b^T with Y_b = F_b L
-                    // (rocBLAS, column-major: Y_b is n x rank, ld n)
-                    const int nb = 2 * gc;
-                    {
-                        TimedLaunch tl(h, ls, 30, 2.0 * nd * nd * rank * nb);
-                        const int brc = blas_lowrank_stage1(h, ls, n, rank, nb);
-                        if (brc) return brc;
-                    }
-                    // chunks of `per` Y_b, enough of them to fill the device with
-                    // output tiles; the last chunk is padded with zero Y_b when the
-                    // buffer has room, else everything goes into one product.  The
-                    // chunk products go to the F buffer (free by now), then into K.
-                    const long tiles = (long)((n + 127) / 128) * ((n + 127) / 128);
-                    int nc = (int)std::max(1L, std::min<long>(nb, (kStage2Tiles + tiles - 1) / tiles));
-                    int per = (nb + nc - 1) / nc;
-                    nc = (nb + per - 1) / per;
-                    const size_t tcap = std::max<size_t>((size_t)nb * n2, n2);
-                    if (nc > 1 && (size_t)nc * per * n * rank > tcap) { nc = 1; per = nb; }
-                    if (nc * per > nb)
-                        HIPCHK(launch_fill(h->d_T + (long)nb * n * rank, (long)(nc * per - nb) * n * rank, 0.0, ls));
-                    {
-                        const int brc = blas_lowrank_stage2(h, ls, n, rank, nb, per, nc, h->d_F);
-                        if (brc) return brc;
-                    }
-                    HIPCHK(launch_sum_partials(h->d_F, nc, n, (n + 1) / 2, h->d_Kt, ls));
-                } else if (!use_lr) {
-                    // dense form: T_b = F_b D, K += W_b T_b F_b on the upper tiles (F_b symmetric)
-                    GemmArgs g1{};
-                    g1.M = g1.N = g1.K = n;
-                    g1.A = h->d_F; g1.lda = n; g1.sA = n2;
-                    g1.B = h->d_Dt; g1.ldb = n; g1.sB = 0;
-                    g1.C = h->d_T; g1.ldc = n; g1.sC = n2;
-                    g1.nbatch = 2 * gc; g1.alpha = nullptr; g1.alpha0 = 1.0; g1.reduce = 0; g1.slices = 1;
-                    {
-                        TimedLaunch tl(h, ls, 0, 2.0 * nd * nd * nd * g1.nbatch);
-                        HIPCHK(launch_dgemm(g1, ls));
-                    }
-                    for (int half = 0; half < 2; ++half) {
-                        GemmArgs g2{};
-                        g2.M = g2.N = g2.K = n;
-                        g2.A = h->d_T + (long)half * gc * n2; g2.lda = n; g2.sA = n2;
-                        g2.B = h->d_F + (long)half * gc * n2; g2.ldb = n; g2.sB = n2;
-                        g2.C = h->d_Kt; g2.ldc = n; g2.sC = 0;
-                        g2.nbatch = gc; g2.alpha = nullptr; g2.alpha0 = 1.0; g2.reduce = 1; g2.upper = 1;
-                        g2.slices = std::max(1, std::min(gc, 2048 / std::max(1, upper_tiles)));
-                        TimedLaunch tl(h, ls, 0, nd * (nd + 1.0) * nd * g2.nbatch);
-                        HIPCHK(launch_dgemm(g2, ls));
-                    }
+            if (!wantK) continue;
+            const double nd = (double)n;
+            const int nb = 2 * gc;
+            if (lowrank) {
+                // F_b carries sqrt(W_b), so K += sum_b Y_b Y_b^T with Y_b = F_b L.
+                // Y_b^T = L^T F_b (rows j < rank), stored as Y_b by columns:
+                // column j of Y_b at T + b n cap + j n.
+                GemmArgs g1{};
+                g1.M = cap; g1.N = n; g1.K = n;
+                g1.A = h->d_L; g1.lda = n; g1.sA = 0;
+                g1.B = h->d_F; g1.ldb = n; g1.sB = n2;
+                g1.C = h->d_T; g1.ldc = n; g1.sC = (long)n * cap;
+                g1.nbatch = nb; g1.alpha0 = 1.0; g1.reduce = 0; g1.slices = 1;
+                g1.ctl = h->d_ctl; g1.ctl_mode = 4; g1.role = 2; g1.tile = h->y_tile;
+                {
+                    TimedLaunch tl(h, ls, 30, 2.0 * nd * nd * nb);   // per unit of rank
+                    HIPCHK(launch_dgemm(g1, ls));
                 }
+                // K += sum_b Y_b Y_b^T on the upper tiles, the batch split into
+                // slices (each slice's tile sums added atomically)
+                GemmArgs g2{};
+                g2.M = g2.N = n; g2.K = cap;
+                g2.A = h->d_T; g2.lda = n; g2.sA = (long)n * cap; g2.transA = 1;
+                g2.B = h->d_T; g2.ldb = n; g2.sB = (long)n * cap;
+                g2.C = h->d_Kt; g2.ldc = n; g2.sC = 0;
+                g2.nbatch = nb; g2.alpha0 = 1.0; g2.reduce = 1; g2.upper = 1;
+                g2.slices = (int)std::max(1L, std::min<long>(nb, (kStage2Blocks + upper_tiles - 1) / upper_tiles));
+                g2.ctl = h->d_ctl; g2.ctl_mode = 2; g2.role = 3;
+                {
+                    TimedLaunch tl(h, ls, 31, nd * (nd + 1.0) * nb);   // per unit of rank (upper triangle)
+                    HIPCHK(launch_dgemm(g2, ls));
+                }
+            }
+            // dense form: T_b = F_b D, K += T_b F_b on the upper tiles (F_b symmetric)
+            GemmArgs g1{};
+            g1.M = g1.N = g1.K = n;
+            g1.A = h->d_F; g1.lda = n; g1.sA = n2;
+            g1.B = h->d_Dt; g1.ldb = n; g1.sB = 0;
+            g1.C = h->d_T; g1.ldc = n; g1.sC = n2;
+            g1.nbatch = nb; g1.alpha = nullptr; g1.alpha0 = 1.0; g1.reduce = 0; g1.slices = 1;
+            g1.ctl = h->d_ctl; g1.ctl_mode = lowrank ? 3 : 0;
+            {
+                TimedLaunch tl(h, ls, lowrank ? 3 : 0, 2.0 * nd * nd * nd * g1.nbatch);
+                HIPCHK(launch_dgemm(g1, ls));
+            }
+            for (int half = 0; half < 2; ++half) {
+                GemmArgs g2{};
+                g2.M = g2.N = g2.K = n;
+                g2.A = h->d_T + (long)half * gc * n2; g2.lda = n; g2.sA = n2;
+                g2.B = h->d_F + (long)half * gc * n2; g2.ldb = n; g2.sB = n2;
+                g2.C = h->d_Kt; g2.ldc = n; g2.sC = 0;
+                g2.nbatch = gc; g2.alpha = nullptr; g2.alpha0 = 1.0; g2.reduce = 1; g2.upper = 1;
+                g2.slices = std::max(1, std::min(gc, 2048 / std::max(1, upper_tiles)));
+                g2.ctl = h->d_ctl; g2.ctl_mode = lowrank ? 3 : 0;
+                TimedLaunch tl(h, ls, lowrank ? 3 : 0, nd * (nd + 1.0) * nd * g2.nbatch);
+                HIPCHK(launch_dgemm(g2, ls));
             }
         }
     }
@@ -744,7 +702,7 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
                 HIPCHK(launch_dgemm(g1, ls));
             }
             GemmArgs g2 = g1;
-            g2.A = h->d_T; g2.B = h->d_S; g2.C = h->d_Kt; g2.alpha0 = f; g2.reduce = 1; g2.upper = use_lr ? 0 : 1;
+            g2.A = h->d_T; g2.B = h->d_S; g2.C = h->d_Kt; g2.alpha0 = f; g2.reduce = 1; g2.upper = 1;
             {
                 TimedLaunch tg(h, ls, 0, nd * (nd + 1.0) * nd);
                 HIPCHK(launch_dgemm(g2, ls));
@@ -762,7 +720,7 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
         HIPCHK(launch_final(fa, st));
     }
     if (wantK) {
-        FinalArgs fa{h->d_Y, h->d_Kt, n, nb, kt_block, h->d_inv_ci, h->d_inv_cc, Ko};
+        FinalArgs fa{h->d_Y, h->d_Kt, n, nb, kGemmTile, h->d_inv_ci, h->d_inv_cc, Ko};
         HIPCHK(launch_final(fa, st));
     }
     if (E_J || E_K) {
@@ -1021,27 +979,29 @@ int pbc_jk_stats(const pbc_jk *hc, pbc_jk_counters *out)
         int ctl[4] = {0, 1, 0, 0};
         if (h->lr_ran) std::memcpy(ctl, h->h_ctl, sizeof ctl);
         const bool dense = !h->lr_ran || ctl[1];
-        h->st.lr_rank = dense ? -1.0 : (double)ctl[0];
+        const double rank = dense ? 0.0 : (double)ctl[0];
+        h->st.lr_rank = dense ? -1.0 : rank;
         // the GEMM figures describe the kernel that accumulated the exchange:
-        // rocBLAS Y Y^T (low rank) or k_dgemm<0> (dense form, with the self term)
-        const int main_kind = dense ? 0 : 31;
-        h->st.gemm_kernel = dense ? 0 : 2;
+        // k_dgemm<3> (low rank, K += sum_b Y_b Y_b^T) or k_dgemm<0> (dense form,
+        // with the self term); the y figures the low-rank products Y_b^T = L^T F_b
+        h->st.gemm_kernel = dense ? 0 : 3;
         h->st.t_gemm_ms = h->st.t_sfac_ms = h->st.gemm_flops = h->st.t_chol_ms = 0.0;
-        h->st.t_blas_ms = h->st.blas_flops = 0.0;
-        h->st.n_gemm = h->st.n_blas = 0;
+        h->st.t_y_ms = h->st.y_flops = 0.0;
+        h->st.n_gemm = h->st.n_y = 0;
         for (int k = 0; k < 21; ++k) h->st.t_sr_class_ms[k] = 0.0;
         for (int i = 0; i < h->ntimed; ++i) {
             float ms = 0;
             HIPCHK(hipEventElapsedTime(&ms, h->tev[2 * i], h->tev[2 * i + 1]));
             const int kind = h->tkind[i];
-            if (kind == main_kind) {
+            const bool main = dense ? (kind == 0 || kind == 3) : kind == 31;
+            if (main) {
                 h->st.t_gemm_ms += ms;
-                h->st.gemm_flops += h->tflops[i];
+                h->st.gemm_flops += h->tflops[i] * (kind == 31 ? rank : 1.0);
                 h->st.n_gemm++;
-            } else if (kind == 30) {
-                h->st.t_blas_ms += ms;
-                h->st.blas_flops += h->tflops[i];
-                h->st.n_blas++;
+            } else if (kind == 30 && !dense) {
+                h->st.t_y_ms += ms;
+                h->st.y_flops += h->tflops[i] * rank;
+                h->st.n_y++;
             } else if (kind == 1) {
                 h->st.t_sfac_ms += ms;
             } else if (kind == 4 || kind == 2) {

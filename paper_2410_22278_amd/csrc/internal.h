@@ -31,7 +31,8 @@ struct alignas(32) PairRec {
     double PA[3];   // P - A
     double cpre;    // c_a c_b Nb(a) Nb(b) exp(-ab/p |A-B|^2) * symmetry weight f
     double PB[3];   // P - B(image)
-    double Q;       // local-pair Cauchy-Schwarz value 2^{1/4} pi^{5/4} |Ca Cb| K / p^{5/4}
+    double Q;       // short-range Cauchy-Schwarz factor: sqrt of the largest normalised
+                    // component of the pair's (ab|ab) with the erfc kernel
     double Cb;      // |Ca Cb| K without the symmetry weight (real-space sphere bound)
     double pad[3];   // pad[0] = 1/p
 };

@@ -119,23 +119,33 @@ struct GemmArgs {
     int upper;            // compute only output tiles on or above the diagonal (M == N)
     // Device-side gating by the low-rank control block ctl = {rank, use_dense}:
     // 0 none; 1 skip if use_dense, N = rank; 2 skip if use_dense, K = rank;
-    // 3 skip unless use_dense.
+    // 3 skip unless use_dense; 4 skip if use_dense, M = rank.  The host sizes
+    // the grid for the upper bound of the rank; tiles beyond it return.
     const int *ctl;
     int ctl_mode;
-    int tag;              // with ctl_mode 0: 1 launches the k_dgemm<1> instantiation
+    // Instantiation (one per role, so that profiles tell them apart):
+    // 0 plain products (self term, dense exchange), 1 residual check of the
+    // density factor, 2 Y_b^T = L^T F_b, 3 K += sum_b Y_b Y_b^T.
+    int role;
+    int tile;             // output tile edge, 64 or 128 (0: kGemmTile); products that
+                          // accumulate the upper tiles of K always use kGemmTile
 };
 hipError_t launch_dgemm(const GemmArgs &a, hipStream_t st);
-constexpr int kGemmTile = 128;   // output tile edge of launch_dgemm
+// Edge of the upper blocks in which K is accumulated (and read back by the
+// final assembly), and the default GEMM output tile.
+constexpr int kGemmTile = 64;
 
 // Pivoted Cholesky of a symmetric n x n matrix D ~= L L^T, L stored by
-// columns (column j at L + j * n), run as one launch per column so that the
-// rank never leaves the device.  Stops when the largest remaining diagonal
-// entry is <= tol * max diag(D) or after rmax columns.  ctl (4 ints):
-// {rank, use_dense, done, -}.  work: n + 2 * ceil(n / 64) + 4 doubles and
-// 2 * ceil(n / 64) ints (wi).  use_dense is set when the factor did not
-// converge within rmax columns or D has a diagonal entry below -tol * max.
+// columns (column j at L + j * n), one launch per column (steps after the
+// stop return at once), with the rank and the stop decision kept on the
+// device: nothing is read back to the host.  Stops when the largest
+// remaining diagonal entry is <= tol * max diag(D) or after rmax columns.
+// ctl (4 ints): {rank, use_dense, done, -}.  work: n + 2 * ceil(n / 64) + 4
+// doubles and 2 * ceil(n / 64) ints (wi).  use_dense is set when the factor
+// did not converge within rmax columns or D has a diagonal entry below
+// -tol * max.
 hipError_t launch_pchol(const double *D, int n, double tol, int rmax, double *L, double *work, int *wi,
-                        int *ctl, int *h_ctl, hipStream_t st);   // h_ctl: pinned host copy (4 ints)
+                        int *ctl, hipStream_t st);
 // After R = L L^T: sets ctl[1] when max |D - R| exceeds 2 tol max diag(D)
 // plus the rounding allowance 4 n eps max diag(D).
 hipError_t launch_lowrank_check(const double *D, const double *R, int n, const double *work, int *ctl,

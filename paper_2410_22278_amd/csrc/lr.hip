@@ -272,55 +272,68 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs a)
 }
 
 // ---------------------------------------------------------------- FP64 MFMA GEMM
-// Block tile 128 x 128, four waves in a 2 x 2 arrangement, each owning a
-// 64 x 64 sub-tile as 4 x 4 MFMA 16x16x4 accumulators; K staged through LDS
-// in slabs of 16 with the next slab prefetched into registers.
+// Block tile T x T (T = 64 or 128), four waves in a 2 x 2 arrangement, each
+// owning a T/2 x T/2 sub-tile as (T/32) x (T/32) MFMA 16x16x4 accumulators;
+// K staged through LDS in slabs of 16 with the next slab prefetched into
+// registers.  Small tiles keep more workgroups resident per CU, which hides
+// the barrier and load latency behind the other workgroups' matrix work.
 // Operand layout of v_mfma_f64_16x16x4f64 (lane l): A[l & 15][l >> 4],
 // B[l >> 4][l & 15]; result register r holds D[(l >> 4) + 4 r][l & 15].
-constexpr int GBM = 128, GBN = 128, GBK = 16, GPAD = 2;
+constexpr int GBK = 16, GPAD = 2;
 
-// GATE (separate instantiations, so that profiles tell the roles apart):
-// 0 plain (self term, dense exchange), 1 low-rank exchange accumulation and
-// its residual check.
-template <int GATE>
+// ROLE (separate instantiations, so that profiles tell the roles apart):
+// 0 plain (self term, dense exchange), 1 residual check of the density
+// factor, 2 Y_b^T = L^T F_b, 3 K += sum_b Y_b Y_b^T (low-rank exchange).
+template <int ROLE, int T>
 __global__ __launch_bounds__(256) void k_dgemm(GemmArgs g)
 {
-    __shared__ double As[GBK][GBM + GPAD];
-    __shared__ double Bs[GBK][GBN + GPAD];
-    if (g.upper && blockIdx.y > blockIdx.x) return;
-    int N = g.N, K = g.K;
+    constexpr int VEC = T * GBK / 256;   // values staged per thread and operand
+    constexpr int WT = T / 2;            // wave sub-tile edge
+    constexpr int NF = WT / 16;          // MFMA tiles per wave and dimension
+    __shared__ double As[GBK][T + GPAD];
+    __shared__ double Bs[GBK][T + GPAD];
+    int M = g.M, N = g.N, K = g.K;
     if (g.ctl_mode) {
         const int use_dense = g.ctl[1];
         if (g.ctl_mode == 3 ? !use_dense : use_dense) return;
-        if (g.ctl_mode == 1) N = g.ctl[0];
-        if (g.ctl_mode == 2) K = g.ctl[0];
+        if (g.ctl_mode == 1) N = min(N, g.ctl[0]);
+        if (g.ctl_mode == 2) K = min(K, g.ctl[0]);
+        if (g.ctl_mode == 4) M = min(M, g.ctl[0]);
     }
-    const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
-    if (n0 >= N) return;
+    // persistent grid: each workgroup strides over the (tile column, tile
+    // row, batch or slice) space sized by the host's upper bounds; skipped
+    // tiles are uniform over the workgroup
+    const int nx = (g.N + T - 1) / T, ny = (g.M + T - 1) / T;
+    const long nxy = (long)nx * ny, total = nxy * (g.reduce ? g.slices : g.nbatch);
+    for (long vb = blockIdx.x; vb < total; vb += gridDim.x) {
+    const int tx = (int)(vb % nx), ty = (int)((vb / nx) % ny), tz = (int)(vb / nxy);
+    if (g.upper && ty > tx) continue;
+    const int m0 = ty * T, n0 = tx * T;
+    if (n0 >= N || m0 >= M) continue;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int wm = wave >> 1, wn = wave & 1;
     const int lr = lane & 15, lk = lane >> 4;
     int b0, b1;
     if (g.reduce) {
         int per = (g.nbatch + g.slices - 1) / g.slices;
-        b0 = blockIdx.z * per;
+        b0 = tz * per;
         b1 = min(g.nbatch, b0 + per);
     } else {
-        b0 = blockIdx.z;
+        b0 = tz;
         b1 = b0 + 1;
     }
-    dbl4 acc[4][4];
+    dbl4 acc[NF][NF];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < NF; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < NF; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
 
-    // each thread stages 8 A values (one row, 8 consecutive k) and 8 B values
-    const int am = tid >> 1, ak = (tid & 1) * 8;
-    const int bk = tid >> 4, bn = (tid & 15) * 8;
-    const int tn = tid >> 1, tk = (tid & 1) * 8;   // transposed B staging
-    const int tam = (tid & 15) * 8, tak = tid >> 4; // transposed A staging
-    double ra[8], rb[8];
+    // staging maps: VEC consecutive values along the contiguous dimension
+    const int am = tid / (GBK / VEC), ak = (tid % (GBK / VEC)) * VEC;     // A (m, k), k contiguous
+    const int tak = tid / (T / VEC), tam = (tid % (T / VEC)) * VEC;      // A (m, k), m contiguous
+    const int bk = tid / (T / VEC), bn = (tid % (T / VEC)) * VEC;        // B (k, n), n contiguous
+    const int tn = tid / (GBK / VEC), tk = (tid % (GBK / VEC)) * VEC;    // B (k, n), k contiguous
+    double ra[VEC], rb[VEC];
     const int nk = (K + GBK - 1) / GBK;
     for (int b = b0; b < b1; ++b) {
         const double *A = g.A + (long)b * g.sA;
@@ -331,29 +344,29 @@ __global__ __launch_bounds__(256) void k_dgemm(GemmArgs g)
             if (g.transA) {
                 const int gk = k0 + tak;
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
+                for (int u = 0; u < VEC; ++u) {
                     int gm = m0 + tam + u;
-                    ra[u] = (gm < g.M && gk < K) ? A[(long)gk * g.lda + gm] : 0.0;
+                    ra[u] = (gm < M && gk < K) ? A[(long)gk * g.lda + gm] : 0.0;
                 }
             } else {
                 const int gm = m0 + am;
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
+                for (int u = 0; u < VEC; ++u) {
                     int gk = k0 + ak + u;
-                    ra[u] = (gm < g.M && gk < K) ? A[(long)gm * g.lda + gk] : 0.0;
+                    ra[u] = (gm < M && gk < K) ? A[(long)gm * g.lda + gk] : 0.0;
                 }
             }
             if (g.transB) {
                 const int gn = n0 + tn;
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
+                for (int u = 0; u < VEC; ++u) {
                     int gk2 = k0 + tk + u;
                     rb[u] = (gk2 < K && gn < N) ? B[(long)gn * g.ldb + gk2] : 0.0;
                 }
             } else {
                 const int gk = k0 + bk;
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
+                for (int u = 0; u < VEC; ++u) {
                     int gn = n0 + bn + u;
                     rb[u] = (gk < K && gn < N) ? B[(long)gk * g.ldb + gn] : 0.0;
                 }
@@ -364,59 +377,64 @@ __global__ __launch_bounds__(256) void k_dgemm(GemmArgs g)
             __syncthreads();
             if (g.transA) {
 #pragma unroll
-                for (int u = 0; u < 8; ++u) As[tak][tam + u] = alpha * ra[u];
+                for (int u = 0; u < VEC; ++u) As[tak][tam + u] = alpha * ra[u];
             } else {
 #pragma unroll
-                for (int u = 0; u < 8; ++u) As[ak + u][am] = alpha * ra[u];
+                for (int u = 0; u < VEC; ++u) As[ak + u][am] = alpha * ra[u];
             }
             if (g.transB) {
 #pragma unroll
-                for (int u = 0; u < 8; ++u) Bs[tk + u][tn] = rb[u];
+                for (int u = 0; u < VEC; ++u) Bs[tk + u][tn] = rb[u];
             } else {
 #pragma unroll
-                for (int u = 0; u < 8; ++u) Bs[bk][bn + u] = rb[u];
+                for (int u = 0; u < VEC; ++u) Bs[bk][bn + u] = rb[u];
             }
             __syncthreads();
             if (kt + 1 < nk) load(kt + 1);
 #pragma unroll
             for (int kk = 0; kk < GBK; kk += 4) {
-                double af[4], bf[4];
+                double af[NF], bf[NF];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) af[i] = As[kk + lk][wm * 64 + i * 16 + lr];
+                for (int i = 0; i < NF; ++i) af[i] = As[kk + lk][wm * WT + i * 16 + lr];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) bf[j] = Bs[kk + lk][wn * 64 + j * 16 + lr];
+                for (int j = 0; j < NF; ++j) bf[j] = Bs[kk + lk][wn * WT + j * 16 + lr];
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
+                for (int i = 0; i < NF; ++i)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
+                    for (int j = 0; j < NF; ++j)
                         acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
             }
         }
         if (!g.reduce) {
             double *C = g.C + (long)b * g.sC;
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < NF; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
+                for (int j = 0; j < NF; ++j)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        int gm = m0 + wm * 64 + i * 16 + lk + 4 * r;
-                        int gn = n0 + wn * 64 + j * 16 + lr;
-                        if (gm < g.M && gn < N) C[(long)gm * g.ldc + gn] = acc[i][j][r];
+                        int gm = m0 + wm * WT + i * 16 + lk + 4 * r;
+                        int gn = n0 + wn * WT + j * 16 + lr;
+                        if (gm < M && gn < N) C[(long)gm * g.ldc + gn] = acc[i][j][r];
                     }
+#pragma unroll
+            for (int i = 0; i < NF; ++i)
+#pragma unroll
+                for (int j = 0; j < NF; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
         }
     }
     if (g.reduce && b1 > b0) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < NF; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < NF; ++j)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    int gm = m0 + wm * 64 + i * 16 + lk + 4 * r;
-                    int gn = n0 + wn * 64 + j * 16 + lr;
-                    if (gm < g.M && gn < N) atomicAdd(&g.C[(long)gm * g.ldc + gn], acc[i][j][r]);
+                    int gm = m0 + wm * WT + i * 16 + lk + 4 * r;
+                    int gn = n0 + wn * WT + j * 16 + lr;
+                    if (gm < M && gn < N) atomicAdd(&g.C[(long)gm * g.ldc + gn], acc[i][j][r]);
                 }
+    }
     }
 }
 
@@ -659,7 +677,7 @@ __global__ __launch_bounds__(256) void k_lowrank_check(const double *D, const do
 }  // namespace
 
 hipError_t launch_pchol(const double *D, int n, double tol, int rmax, double *L, double *work, int *wi,
-                        int *ctl, int *h_ctl, hipStream_t st)
+                        int *ctl, hipStream_t st)
 {
     const int nblk = (n + kCholRows - 1) / kCholRows;
     if (n <= kCholSingleMax) {
@@ -667,20 +685,10 @@ hipError_t launch_pchol(const double *D, int n, double tol, int rmax, double *L,
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_pchol_init, dim3(1), dim3(1024), 0, st, D, n, tol, work, wi, ctl);
-    // columns in chunks; between chunks the host reads the stop flag, so
-    // that no launches are queued far beyond the rank
-    constexpr int kChunk = 64;
-    for (int k0 = 0; k0 < rmax; k0 += kChunk) {
-        const int k1 = std::min(rmax, k0 + kChunk);
-        for (int k = k0; k < k1; ++k)
-            hipLaunchKernelGGL(k_pchol_step, dim3(nblk), dim3(256), 0, st, D, n, k, L, work, wi, ctl);
-        if (k1 < rmax) {
-            hipError_t e = hipMemcpyAsync(h_ctl, ctl, 4 * sizeof(int), hipMemcpyDeviceToHost, st);
-            if (e == hipSuccess) e = hipStreamSynchronize(st);
-            if (e != hipSuccess) return e;
-            if (h_ctl[2]) break;
-        }
-    }
+    // every column up to rmax is queued; the steps after the stop return at
+    // their first instruction (the caller keeps rmax near the expected rank)
+    for (int k = 0; k < rmax; ++k)
+        hipLaunchKernelGGL(k_pchol_step, dim3(nblk), dim3(256), 0, st, D, n, k, L, work, wi, ctl);
     hipLaunchKernelGGL(k_pchol_fin, dim3(1), dim3(256), 0, st, n, rmax, (const double *)work, (const int *)wi, ctl);
     return hipGetLastError();
 }
@@ -733,14 +741,32 @@ hipError_t launch_jlr(const double *F, const double *rho, const double *Gw, int 
     return hipGetLastError();
 }
 
+// Workgroups of the persistent GEMM grid: enough to keep every CU busy with
+// several resident workgroups, few enough that a launch gated off on the
+// device costs little.
+constexpr long kGemmGrid = 2048;
+
+template <int T>
+hipError_t launch_dgemm_t(const GemmArgs &a, hipStream_t st)
+{
+    const long z = a.reduce ? a.slices : a.nbatch;
+    const long tiles = (long)((a.N + T - 1) / T) * ((a.M + T - 1) / T) * z;
+    dim3 grid((unsigned)std::min(tiles, kGemmGrid));
+    switch (a.role) {
+        case 1: hipLaunchKernelGGL((k_dgemm<1, T>), grid, dim3(256), 0, st, a); break;
+        case 2: hipLaunchKernelGGL((k_dgemm<2, T>), grid, dim3(256), 0, st, a); break;
+        case 3: hipLaunchKernelGGL((k_dgemm<3, T>), grid, dim3(256), 0, st, a); break;
+        default: hipLaunchKernelGGL((k_dgemm<0, T>), grid, dim3(256), 0, st, a); break;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_dgemm(const GemmArgs &a, hipStream_t st)
 {
     if (a.M <= 0 || a.N <= 0 || a.K <= 0 || a.nbatch <= 0) return hipSuccess;
-    int z = a.reduce ? a.slices : a.nbatch;
-    dim3 grid((a.N + GBN - 1) / GBN, (a.M + GBM - 1) / GBM, z);
-    if (a.ctl_mode == 0 && !a.tag) hipLaunchKernelGGL(k_dgemm<0>, grid, dim3(256), 0, st, a);
-    else hipLaunchKernelGGL(k_dgemm<1>, grid, dim3(256), 0, st, a);
-    return hipGetLastError();
+    // products that write the upper tiles of K use the K block size
+    const int t = (a.upper || a.tile == 0) ? kGemmTile : a.tile;
+    return t == 64 ? launch_dgemm_t<64>(a, st) : launch_dgemm_t<128>(a, st);
 }
 
 hipError_t launch_fill(double *p, long n, double v, hipStream_t st)

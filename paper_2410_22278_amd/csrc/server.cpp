@@ -102,9 +102,12 @@ int copy_inputs(const pbc_cell *cell, const pbc_atoms *atoms, const pbc_basis *b
     return 0;
 }
 
-// A cell known to the server.  h == nullptr while its setup is being made.
+// A cell known to the server.  h == nullptr while its setup is being made:
+// it is then a placeholder that belongs to the request `owner` (requests for
+// the same cell with other densities share the entry and wait for it).
 struct Cell {
     pbc_jk *h = nullptr;
+    unsigned long long owner = 0;
     bool busy = false;
     unsigned long long last_use = 0;
     size_t bytes = 0;
@@ -170,12 +173,13 @@ void finish(pbc_jk_server *s, Request *r, int status, const std::string &msg)
     s->cv_done.notify_all();
 }
 
-// Drops the placeholder cell of a request that held one and returns the
-// prepared handle for deletion outside the lock (lock held).
+// Drops the placeholder cell that request r created, if it still holds one
+// (a placeholder of another request for the same cell is left alone), and
+// returns r's prepared handle for deletion outside the lock (lock held).
 pbc_jk *drop_placeholder(pbc_jk_server *s, Request *r)
 {
     auto it = s->cells.find(r->in.sig);
-    if (it != s->cells.end() && it->second->h == nullptr) {
+    if (it != s->cells.end() && it->second->h == nullptr && it->second->owner == r->id) {
         delete it->second;
         s->cells.erase(it);
     }
@@ -232,7 +236,8 @@ Action pick(pbc_jk_server *s, Request *&r, Cell *&cell, std::vector<pbc_jk *> &t
             continue;
         }
         auto ce = s->cells.find(q->in.sig);
-        const bool own_placeholder = q->prepared && ce != s->cells.end() && ce->second->h == nullptr;
+        const bool own_placeholder =
+            q->prepared && ce != s->cells.end() && ce->second->h == nullptr && ce->second->owner == q->id;
         if (ce != s->cells.end() && !own_placeholder) {
             if (ce->second->busy) { ++it; continue; }
             ce->second->busy = true;
@@ -245,6 +250,7 @@ Action pick(pbc_jk_server *s, Request *&r, Cell *&cell, std::vector<pbc_jk *> &t
         if (!q->prepared) {
             cell = new Cell();
             cell->busy = true;
+            cell->owner = q->id;
             s->cells[q->in.sig] = cell;
             r = q;
             s->queue.erase(it);

@@ -115,6 +115,56 @@ void herm1(int la, int lb, double p, double xa, double xb, double *E)
 
 bool finite(double x) { return std::isfinite(x); }
 
+// Largest component of the short-range self-integral of one primitive pair,
+// (ab|ab) with the erfc(w r)/r kernel, for monomial Gaussians with
+// E^{00}_0 = 1 (the pair's Gaussian factor and normalisation are applied by
+// the caller), times the square of the component normalisation ratios.
+// At zero separation the Hermite integrals reduce to
+//   R_{tuv}(0) = (t-1)!! (u-1)!! (v-1)!! R^{(t+u+v)/2}_{000}(0)   (t, u, v even),
+//   R^m_{000}(0) = ((-2 rho)^m - c (-2 a')^m) / (2m + 1),  rho = p/2,
+// (eq. R_recursion at X = Y = Z = 0, and F_m(0) = 1/(2m+1)), and the
+// four-index sum factorises per axis into S[k] = sum_{t+s=k} (-1)^s E_t E_s.
+// By the Cauchy-Schwarz inequality of Sec. 2.4 (eq. local_cauchy_schwarz_bound,
+// which holds for the positive definite erfc kernel) the square root bounds
+// every short-range quartet term of the pair.
+double sr_self_max(int la, int lb, double a, double b, const double PA[3], const double PB[3], double omega)
+{
+    const double p = a + b, rho = 0.5 * p, w2 = omega * omega;
+    const double ap = rho * w2 / (rho + w2), c = omega / std::sqrt(rho + w2);
+    const int lab = la + lb, nt = lab + 1;
+    double R0[2 * 2 * kMaxL + 1];
+    for (int m = 0; m <= 2 * lab; ++m)
+        R0[m] = (std::pow(-2.0 * rho, m) - c * std::pow(-2.0 * ap, m)) / (2 * m + 1);
+    const double dfact[9] = {1.0, 1.0, 1.0, 3.0, 3.0, 15.0, 15.0, 105.0, 105.0};   // (k-1)!! for even k
+    double E[3][(kMaxL + 1) * (kMaxL + 1) * (2 * kMaxL + 1)];
+    for (int x = 0; x < 3; ++x) herm1(la, lb, p, PA[x], PB[x], E[x]);
+    double best = 0.0;
+    for (int ia = 0; ia < ncart(la); ++ia)
+        for (int ib = 0; ib < ncart(lb); ++ib) {
+            int cA[3], cB[3];
+            comp(la, ia, cA);
+            comp(lb, ib, cB);
+            double Sx[3][2 * 2 * kMaxL + 1];
+            for (int x = 0; x < 3; ++x) {
+                const int nx = cA[x] + cB[x];
+                const double *e = E[x] + (cA[x] * (lb + 1) + cB[x]) * nt;
+                for (int k = 0; k <= 2 * nx; ++k) Sx[x][k] = 0.0;
+                for (int t = 0; t <= nx; ++t)
+                    for (int u = 0; u <= nx; ++u) Sx[x][t + u] += ((u & 1) ? -1.0 : 1.0) * e[t] * e[u];
+            }
+            double I = 0.0;
+            for (int kx = 0; kx <= 2 * (cA[0] + cB[0]); kx += 2)
+                for (int ky = 0; ky <= 2 * (cA[1] + cB[1]); ky += 2)
+                    for (int kz = 0; kz <= 2 * (cA[2] + cB[2]); kz += 2)
+                        I += Sx[0][kx] * Sx[1][ky] * Sx[2][kz] * dfact[kx] * dfact[ky] * dfact[kz] *
+                             R0[(kx + ky + kz) / 2];
+            I *= 2.0 * std::pow(kPi, 2.5) / (p * p * std::sqrt(2.0 * p));
+            const double r = rho_comp(cA) * rho_comp(cB);
+            best = std::max(best, I * r * r);
+        }
+    return best;
+}
+
 }  // namespace
 
 double boys_host(int m, double T)
@@ -308,7 +358,11 @@ int build_setup(const double *cell, int natom, const double *xyz, int nshell, co
                         }
                         t.rec.p = p;
                         t.rec.cpre = ca * cb * nbase(a, la) * nbase(b, lb) * g * fw;
-                        t.rec.Q = Y0 * g;
+                        // short-range Cauchy-Schwarz factor of the pair (quartet screen)
+                        double pa[3] = {t.rec.PA[0], t.rec.PA[1], t.rec.PA[2]};
+                        double pb[3] = {t.rec.PB[0], t.rec.PB[1], t.rec.PB[2]};
+                        t.rec.Q = std::fabs(ca * cb) * nbase(a, la) * nbase(b, lb) * g *
+                                  std::sqrt(sr_self_max(la, lb, a, b, pa, pb, S.omega));
                         t.rec.Cb = Cab * g;
                         t.rec.pad[0] = 1.0 / p;
                         t.rec.pad[1] = t.rec.pad[2] = 0.0;

@@ -278,6 +278,7 @@ __global__ __launch_bounds__(64) void k_sr_coop(SRArgs a)
         atomicAdd(&a.counters[0], cnt_q);
         atomicAdd(&a.counters[1], cnt_t);
         atomicAdd(&a.counters[2 + a.slot], cnt_t);
+        atomicAdd(&a.counters[24 + a.slot], cnt_q);
     }
 }
 

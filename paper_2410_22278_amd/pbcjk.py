@@ -60,8 +60,8 @@ class pbc_jk_counters(ctypes.Structure):
                 ("t_other_ms", c_double), ("t_gemm_ms", c_double), ("gemm_flops", c_double),
                 ("n_gemm", c_int), ("t_sfac_ms", c_double), ("terms_class", c_double * 21),
                 ("n_group_pairs", c_double), ("lr_rank", c_double), ("t_chol_ms", c_double),
-                ("gemm_kernel", c_int), ("t_sr_class_ms", c_double * 21), ("t_blas_ms", c_double),
-                ("blas_flops", c_double), ("n_blas", c_int), ("sr_fold_mask", c_int),
+                ("gemm_kernel", c_int), ("t_sr_class_ms", c_double * 21), ("t_y_ms", c_double),
+                ("y_flops", c_double), ("n_y", c_int), ("sr_fold_mask", c_int),
                 ("sr_kernel_mask", c_int)]
 
 
@@ -192,11 +192,18 @@ def pbc_jk_create(cell, xyz, shell_atom, shell_l, shell_pure, shell_nprim, exps,
     return h.value
 
 
+def _square(n: int, what: str, shape):
+    if tuple(shape) != (n, n):
+        raise ValueError(f"{what} must be {n} x {n} (the handle's AO count), got {tuple(shape)}")
+
+
 def pbc_jk_build(h: int, D, want_J: bool = True, want_K: bool = True):
     """Host-memory build: returns (J, K, E_J, E_K)."""
     lib = load()
+    n = pbc_jk_nbf(h)
+    _check(n if n < 0 else 0)
     D = np.ascontiguousarray(D, dtype=np.float64)
-    n = D.shape[0]
+    _square(n, "D", D.shape)
     J = np.empty((n, n)) if want_J else None
     K = np.empty((n, n)) if want_K else None
     ej, ek = c_double(), c_double()
@@ -206,21 +213,39 @@ def pbc_jk_build(h: int, D, want_J: bool = True, want_K: bool = True):
     return J, K, ej.value, ek.value
 
 
+def _stream_ptr(stream):
+    """hipStream_t of a torch stream (or an integer handle); None means
+    torch's current stream on the current device."""
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _check_device_buffers(h: int, **bufs):
+    import torch
+    n = pbc_jk_nbf(h)
+    _check(n if n < 0 else 0)
+    for name, t in bufs.items():
+        if t is None:
+            continue
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float64 cuda tensor")
+        _square(n, name, t.shape)
+
+
 def pbc_jk_build_device(h: int, dD, dJ=None, dK=None, energies: bool = True, stream=None):
-    """Device-memory build on torch tensors (float64, cuda, contiguous).
+    """Device-memory build on torch tensors (float64, cuda, contiguous,
+    nbf x nbf), queued on `stream` (default: torch's current stream).
     Returns (E_J, E_K) when energies, else None (asynchronous)."""
     lib = load()
-    for t in (dD, dJ, dK):
-        if t is not None and (t.dtype.itemsize != 8 or not t.is_cuda or not t.is_contiguous()):
-            raise ValueError("device buffers must be contiguous float64 cuda tensors")
+    _check_device_buffers(h, dD=dD, dJ=dJ, dK=dK)
     ej, ek = c_double(), c_double()
-    sp = None
-    if stream is not None:
-        sp = c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
     rc = lib.pbc_jk_build_device(c_void_p(h), c_void_p(dD.data_ptr()),
                                  c_void_p(dJ.data_ptr()) if dJ is not None else None,
                                  c_void_p(dK.data_ptr()) if dK is not None else None,
-                                 byref(ej) if energies else None, byref(ek) if energies else None, sp)
+                                 byref(ej) if energies else None, byref(ek) if energies else None,
+                                 _stream_ptr(stream))
     _check(rc)
     return (ej.value, ek.value) if energies else None
 
@@ -317,7 +342,8 @@ class Server:
                                       system.shell_pure, system.shell_nprim, system.exps, system.coefs,
                                       system.thr)
         D = np.ascontiguousarray(system.D if D is None else D, dtype=np.float64)
-        n = D.shape[0]
+        n = int(system.nbf)
+        _square(n, "D", D.shape)
         J = np.empty((n, n)) if want_J else None
         K = np.empty((n, n)) if want_K else None
         ej, ek = c_double(), c_double()

@@ -5,7 +5,6 @@ library/closed-form values, textbook identities, exact quadrature, brute
 force, or invariances a mistake would break.  None needs a GPU.
 """
 import math
-import os
 
 import numpy as np
 import pytest
@@ -495,7 +494,7 @@ def test_row_subset_is_exact(oracle_mod):
     assert np.abs(sub["K"][rows] - full["K"][rows]).max() < 1e-13
 
 
-@pytest.mark.skipif(not os.environ.get("PBCJK_SLOW"), reason="two cfg1 oracle runs (~2 min); set PBCJK_SLOW=1")
+@pytest.mark.slow
 def test_cutoff_convergence_tiny_config(oracle_mod):
     """cfg1's own truncation (delta 1e-10, 10 A image cap, |G| <= 3) against a
     tighter run (delta 1e-12, no caps): the difference is the truncation error
