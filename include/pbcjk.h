@@ -158,6 +158,8 @@ typedef struct {
     int sr_kernel_mask;  /* last build: bit k set when class pair k ran one wavefront per group
                             pair (else one lane per group pair, in component slices for the
                             large d pairs)                                                     */
+    int sr_jengine_mask; /* last build: bit k set when class pair k ran the J-engine (builds
+                            without K: Hermite densities of the pairs, no Cartesian block)     */
 } pbc_jk_counters;
 
 /* Creates a handle: validates and copies the inputs, builds the local pair
@@ -185,6 +187,25 @@ int pbc_jk_build(pbc_jk *h, const double *D, double *J, double *K, double *E_J, 
  * with the build queued.  D is not checked for symmetry on this path. */
 int pbc_jk_build_device(pbc_jk *h, const double *dD, double *dJ, double *dK,
                         double *E_J, double *E_K, void *stream);
+
+/* Gamma-point one-electron terms on the handle's pair list, lattice and
+ * reciprocal vectors (host outputs, nbf x nbf, each may be NULL):
+ *   S     overlap (Sec. 2.2, eq. pbc_overlap_formula);
+ *   T     kinetic energy (supporting information, eq. kinetic_formula);
+ *   V     nuclear attraction -sum_C Z_C <mu| v(r - C) |nu>, v the periodic
+ *         Coulomb potential of a unit point charge with its G = 0 term
+ *         removed, Ewald-split as in Sec. 2.3 (eq. pbc_v1e_general_final:
+ *         real-space erfc sum inside the sphere of eq.
+ *         pbc_v1e_real_cutoff_implementation, reciprocal sum over the
+ *         handle's G sphere, self term -(pi/(V w^2)) sum_C q_C S);
+ *   E_nuc nuclear repulsion energy (Sec. 2.9, eq. nuclear_repulsion_energy),
+ *         real-space radius from erfc(x) < (2/sqrt(pi)) e^{-x^2}/x and the
+ *         handle's G sphere.
+ * Z are the charges given in pbc_atoms.charge at creation; V or E_nuc
+ * without them is PBC_JK_EINVAL.  Uses the handle's work buffers and its own
+ * stream; synchronous.  Calls on one handle must not overlap (builds
+ * included). */
+int pbc_jk_one_electron(pbc_jk *h, double *S, double *T, double *V, double *E_nuc);
 
 /* Releases the handle and its device memory.  NULL is accepted. */
 void pbc_jk_destroy(pbc_jk *h);

@@ -80,6 +80,8 @@ def _load():
         lib.orc_lattice_sphere.restype = c_long
         lib.orc_ewald_energy.argtypes = [c_int, dp, dp, dp, c_double, c_double, c_double]
         lib.orc_ewald_energy.restype = c_double
+        lib.orc_one_electron.argtypes = [POINTER(OrcSys), dp, dp, dp, dp]
+        lib.orc_one_electron.restype = c_int
         _lib = lib
     return _lib
 
@@ -410,3 +412,51 @@ def eri_tensor(system, omega=None, thr=None) -> np.ndarray:
     Tc = Tsr + Tlr + Tself
     T = sph_transform(system)
     return np.einsum("ai,bj,ck,dl,ijkl->abcd", T, T, T, T, Tc, optimize=True)
+
+
+def one_electron(system, omega=None, thr=None, charges=None, parts: str = "sr,lr,self") -> dict:
+    """Gamma-point overlap S, kinetic T, nuclear attraction V and the nuclear
+    repulsion energy E_nuc of `system` (spherical where the basis says so).
+
+    V_{mu nu} = sum_C q_C <mu| v(r - C) |nu> with q_C = -Z_C (electrons
+    attracted by nuclei of charge Z = system.charge unless `charges` is
+    given) and v the Ewald-split periodic Coulomb potential of a point charge
+    with its G = 0 term removed (Sec. 2.3, eq. pbc_v1e_general_final):
+    real-space erfc sum (the C loops), reciprocal sum over the same G list as
+    the ERIs, and the self term -(pi/(V w^2)) sum_C q_C S.  E_nuc is the
+    Ewald energy of the nuclei (Sec. 2.9, eq. nuclear_repulsion_energy)."""
+    s = _Sys(system, omega, thr)
+    lib = _load()
+    Z = np.ascontiguousarray(system.charge, dtype=np.float64)
+    q = -Z if charges is None else np.ascontiguousarray(charges, dtype=np.float64)
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    nbc = lib.orc_nbf_cart(ctypes.byref(s.c))
+    S = np.zeros((nbc, nbc)); T = np.zeros((nbc, nbc)); Vsr = np.zeros((nbc, nbc))
+    if lib.orc_one_electron(ctypes.byref(s.c), _dp(q), _dp(S), _dp(T), _dp(Vsr)) != 0:
+        raise ValueError("oracle rejected the basis")
+    want = set(parts.split(","))
+    if "sr" not in want:
+        Vsr[:] = 0.0
+    Vlr = np.zeros((nbc, nbc))
+    if "lr" in want:
+        G, w = glist(system, omega, thr)
+        xyz = np.asarray(system.xyz, dtype=np.float64)
+        for g0 in range(0, G.shape[0], 64):
+            Gc = np.ascontiguousarray(G[g0:g0 + 64])
+            F = structure_factors(system, Gc, omega, thr)
+            for k in range(Gc.shape[0]):
+                # rho_n(G) = sum_C q_C e^{-i G.C}; v's Fourier sum gives
+                # sum_G w_G Re(conj(F_G) rho_n(G))
+                rho_n = np.sum(q * np.exp(-1j * (xyz @ Gc[k])))
+                Vlr += w[g0 + k] * np.real(np.conj(F[k]) * rho_n)
+    Vself = np.zeros((nbc, nbc))
+    if "self" in want:
+        Vself = -np.pi / (s.volume * s.omega ** 2) * np.sum(q) * S
+    Vc = Vsr + Vlr + Vself
+    Tm = sph_transform(system)
+    out = dict(S=Tm @ S @ Tm.T, T=Tm @ T @ Tm.T, V=Tm @ Vc @ Tm.T, V_sr=Tm @ Vsr @ Tm.T,
+               V_lr=Tm @ Vlr @ Tm.T, V_self=Tm @ Vself @ Tm.T, Sc=S, Tc=T, Vc=Vc)
+    t = thr if thr is not None else system.thr
+    out["E_nuc"] = ewald_energy(system.xyz, Z, system.cell, s.omega, t.ewald_R, t.ewald_K)
+    return out
+

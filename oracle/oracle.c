@@ -1127,3 +1127,151 @@ double orc_ewald_energy(int natom, const double *xyz, const double *q, const dou
         }
     return E;
 }
+
+/* ---------------------------------------------------------------------- */
+/* one-electron matrices at the Gamma point                                 */
+/* ---------------------------------------------------------------------- */
+typedef struct { int lab; double p, omega, rad2, rcap2, P[3], C[3]; const double *e[3]; int nt;
+                 int la, lb; double *acc; long nimg; } v_user;
+
+/* One lattice image R_C of the short-range point-charge sum: adds
+ * sum_t E^{ab}_t R^SR_t(p, L), L = P - C + R_C, to every component of the
+ * pair's block. */
+static void v_cb(const double R[3], const int n[3], void *u_)
+{
+    (void)n;
+    v_user *u = (v_user *)u_;
+    double L[3];
+    for (int x = 0; x < 3; ++x) L[x] = u->P[x] - u->C[x] + R[x];
+    double L2 = L[0] * L[0] + L[1] * L[1] + L[2] * L[2];
+    if (!(L2 < u->rad2)) return;
+    if (u->rcap2 > 0 && L2 > u->rcap2) return;
+    int n1 = u->lab + 1;
+    double R000[ORC_MAXLQ + 1];
+    /* short-range point-charge kernel: the Boys split of Sec. 2.3 (eq.
+     * boys_function_split) with the pair exponent p in place of rho */
+    kernel_R000(KER_SR, u->lab, u->p, u->omega, L2, R000);
+    double Rt[(ORC_MAXLQ + 1) * (ORC_MAXLQ + 1) * (ORC_MAXLQ + 1)];
+    hermite_R(u->lab, R000, L, Rt);
+    for (int i = 0; i < ncart(u->la); ++i) {
+        int ca[3]; cart_comp(u->la, i, ca);
+        for (int j = 0; j < ncart(u->lb); ++j) {
+            int cb[3]; cart_comp(u->lb, j, cb);
+            const double *ex = u->e[0] + (ca[0] * (u->lb + 1) + cb[0]) * u->nt;
+            const double *ey = u->e[1] + (ca[1] * (u->lb + 1) + cb[1]) * u->nt;
+            const double *ez = u->e[2] + (ca[2] * (u->lb + 1) + cb[2]) * u->nt;
+            double s = 0.0;
+            for (int t = 0; t <= ca[0] + cb[0]; ++t)
+            for (int v = 0; v <= ca[1] + cb[1]; ++v)
+            for (int w = 0; w <= ca[2] + cb[2]; ++w)
+                s += ex[t] * ey[v] * ez[w] * Rt[(t * n1 + v) * n1 + w];
+            u->acc[i * ncart(u->lb) + j] += s;
+        }
+    }
+    u->nimg++;
+}
+
+/* Gamma-point overlap S, kinetic T and the real-space part of the
+ * point-charge potential matrix Vsr over the local primitive pairs of the
+ * ERI pair list (ordered pairs, contracted and normalised components):
+ *   S   += c_a c_b N_i N_j (pi/p)^{3/2} E^{ix jx}_0 E^{iy jy}_0 E^{iz jz}_0
+ *          (Sec. 2.2, eq. pbc_overlap_formula);
+ *   T   += c_a c_b N_i N_j (pi/p)^{3/2} t_local, t_local of the SI
+ *          (eq. kinetic_formula), whose E^{i, j+-2}_0 come from the same
+ *          E recurrences with the second index raised by two;
+ *   Vsr += q_C c_a c_b N_i N_j (2 pi/p) sum_{R_C} sum_t E^{ab}_t
+ *          [R^0_t(p, L) - w/sqrt(p + w^2) R^0_t(p w^2/(p + w^2), L)],
+ *          L = P - C + R_C, the real-space term of Sec. 2.3 (eq.
+ *          pbc_v1e_general_final), with R_C inside the sphere of eq.
+ *          pbc_v1e_real_cutoff_implementation (C1e = C_a C_b (2 pi/p) K_ab)
+ *          and, when set, |L| <= r_cut.
+ * q: natom point charges (the potential of charge q_C is q_C/|r - C|); q
+ * NULL skips Vsr.  Outputs nbfc x nbfc, overwritten.  Returns 0 or -1. */
+int orc_one_electron(const orc_sys *in, const double *q, double *S, double *T, double *Vsr)
+{
+    ctx_t X;
+    if (ctx_build(in, &X)) { ctx_free(&X); return -1; }
+    long nb = X.nbfc;
+    memset(S, 0, sizeof(double) * nb * nb);
+    memset(T, 0, sizeof(double) * nb * nb);
+    memset(Vsr, 0, sizeof(double) * nb * nb);
+    const double w = in->omega, w2 = w * w;
+#pragma omp parallel
+    {
+        double *Sl = (double *)calloc((size_t)nb * nb, sizeof(double));
+        double *Tl = (double *)calloc((size_t)nb * nb, sizeof(double));
+        double *Vl = (double *)calloc((size_t)nb * nb, sizeof(double));
+#pragma omp for schedule(dynamic, 16)
+        for (long ip = 0; ip < X.npair; ++ip) {
+            const pair_t *P = &X.pair[ip];
+            const int la = P->la, lb = P->lb, na = ncart(la), nbb = ncart(lb);
+            double Na[ORC_MAXNC], Nb[ORC_MAXNC];
+            comp_norms(la, P->a, Na); comp_norms(lb, P->b, Nb);
+            const double cc = P->ca * P->cb, pp = P->p;
+            const double ov = pow(ORC_PI / pp, 1.5);
+            /* E tables with the second index up to lb + 2 (kinetic) */
+            int ntk = la + lb + 3;
+            double Ek[3][3 * 5 * 7];
+            for (int x = 0; x < 3; ++x) {
+                double dab = P->A[x] - P->B[x];
+                hermite_E(la, lb + 2, pp, P->P[x] - P->A[x], P->P[x] - P->B[x],
+                          exp(-P->a * P->b / pp * dab * dab), Ek[x]);
+            }
+#define E0(x, i, j) Ek[x][((i) * (lb + 3) + (j)) * ntk]
+            long aoA = X.sh[P->sa].ao, aoB = X.sh[P->sb].ao;
+            for (int i = 0; i < na; ++i) {
+                int ca[3]; cart_comp(la, i, ca);
+                for (int j = 0; j < nbb; ++j) {
+                    int cb[3]; cart_comp(lb, j, cb);
+                    double e[3], kin = 0.0;
+                    for (int x = 0; x < 3; ++x) e[x] = E0(x, ca[x], cb[x]);
+                    for (int x = 0; x < 3; ++x) {
+                        int jx = cb[x];
+                        double d2 = (jx >= 2 ? -0.5 * jx * (jx - 1) * E0(x, ca[x], jx - 2) : 0.0)
+                                    + (2 * jx + 1) * P->b * E0(x, ca[x], jx)
+                                    - 2.0 * P->b * P->b * E0(x, ca[x], jx + 2);
+                        kin += d2 * e[(x + 1) % 3] * e[(x + 2) % 3];
+                    }
+                    double f = cc * Na[i] * Nb[j] * ov;
+                    Sl[(aoA + i) * nb + aoB + j] += f * e[0] * e[1] * e[2];
+                    Tl[(aoA + i) * nb + aoB + j] += f * kin;
+                }
+            }
+#undef E0
+            if (q) {
+                int sz = (la + 1) * (lb + 1) * (la + lb + 1);
+                const double *ep[3] = {P->E, P->E + sz, P->E + 2 * sz};
+                double c = w / sqrt(pp + w2);
+                double C1e = P->Ca * P->Cb * 2.0 * ORC_PI / pp * P->Kab;
+                double arg = C1e * (1.0 - c) / in->d_ewald_R;
+                if (arg > 1.0) {
+                    double rad2 = (1.0 / pp + 1.0 / w2) * log(arg);
+                    double acc[ORC_MAXNC * ORC_MAXNC];
+                    for (int C = 0; C < in->natom; ++C) {
+                        if (q[C] == 0.0) continue;
+                        memset(acc, 0, sizeof acc);
+                        v_user u = {la + lb, pp, w, rad2, in->r_cut > 0 ? in->r_cut * in->r_cut : 0.0,
+                                    {P->P[0], P->P[1], P->P[2]},
+                                    {in->xyz[3 * C], in->xyz[3 * C + 1], in->xyz[3 * C + 2]},
+                                    {ep[0], ep[1], ep[2]}, la + lb + 1, la, lb, acc, 0};
+                        /* R_C with |R_C - (C - P)| < r */
+                        double cen[3] = {u.C[0] - u.P[0], u.C[1] - u.P[1], u.C[2] - u.P[2]};
+                        enum_sphere(X.lat.M, X.lat.Minv, cen, sqrt(rad2) * (1.0 + 1e-9) + 1e-9, v_cb, &u);
+                        if (!u.nimg) continue;
+                        for (int i = 0; i < na; ++i)
+                            for (int j = 0; j < nbb; ++j)
+                                Vl[(aoA + i) * nb + aoB + j] +=
+                                    q[C] * cc * Na[i] * Nb[j] * 2.0 * ORC_PI / pp * acc[i * nbb + j];
+                    }
+                }
+            }
+        }
+#pragma omp critical
+        {
+            for (long k = 0; k < nb * nb; ++k) { S[k] += Sl[k]; T[k] += Tl[k]; Vsr[k] += Vl[k]; }
+        }
+        free(Sl); free(Tl); free(Vl);
+    }
+    ctx_free(&X);
+    return 0;
+}

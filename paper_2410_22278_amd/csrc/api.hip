@@ -81,6 +81,13 @@ struct pbc_jk {
     double *d_Jt = nullptr, *d_Kt = nullptr, *d_F = nullptr, *d_T = nullptr, *d_rho = nullptr;
     double *d_scal = nullptr, *d_Jo = nullptr, *d_Ko = nullptr;
     unsigned long long *d_dmaxg = nullptr, *d_cnt = nullptr;
+    unsigned long long *stat_cnt = nullptr;   // counters of the last build
+    // J-engine: Hermite densities of every primitive pair (per class, pairs
+    // p0 .. of the class at hd + hd_base[class])
+    double *d_hd = nullptr;
+    double *d_xyz = nullptr, *d_q = nullptr;   // atom positions, point charges -Z (one-electron terms)
+    long hd_base[kNumClass + 1] = {0};
+    int class_p0[kNumClass] = {0};
     // real-space neighbour lists, one segment per class pair
     int *d_nbr_bra = nullptr, *d_nbr_ket = nullptr;
     // low-rank reciprocal exchange: density factor (by columns), work, control
@@ -90,6 +97,7 @@ struct pbc_jk {
     hipEvent_t ev_ctl = nullptr; // recorded after that copy
     int lr_cap = 0;              // columns queued for the last factor (upper bound of its rank)
     int y_tile = 64;             // output tile of the products Y_b^T = L^T F_b
+    double coop_ratio = kCoopRatio;
     int lr_rmax = 0;
     bool lr_ran = false;
     size_t nbr_bytes_needed = 0;   // set once the neighbour lists are counted
@@ -192,7 +200,8 @@ void release_device(pbc_jk *h)
                    (void **)&h->d_Ko, (void **)&h->d_dmaxg, (void **)&h->d_cnt, (void **)&h->d_nbr_bra,
                    (void **)&h->d_nbr_ket, (void **)&h->d_L, (void **)&h->d_pw, (void **)&h->d_pwi,
                    (void **)&h->d_ctl, (void **)&h->d_w64b, (void **)&h->d_w64k, (void **)&h->d_w32b,
-                   (void **)&h->d_w32k, (void **)&h->d_wcnt, (void **)&h->d_ncnt};
+                   (void **)&h->d_w32k, (void **)&h->d_wcnt, (void **)&h->d_ncnt, (void **)&h->d_hd,
+                   (void **)&h->d_xyz, (void **)&h->d_q};
     for (void **p : pp) {
         dfree(h, *p);
         *p = nullptr;
@@ -291,6 +300,12 @@ int create_device(pbc_jk *h)
     if ((rc = upload(h, &h->d_tr_ao, S.tr_ao))) return rc;
     if ((rc = upload(h, &h->d_tr_c, S.tr_c))) return rc;
     if ((rc = upload(h, &h->d_dscale, S.dscale))) return rc;
+    if ((rc = upload(h, &h->d_xyz, S.xyz))) return rc;
+    {
+        std::vector<double> q(S.natom, 0.0);
+        for (size_t i = 0; i < S.charge.size(); ++i) q[i] = -S.charge[i];
+        if ((rc = upload(h, &h->d_q, q))) return rc;
+    }
     // inverse transform: output AO -> up to three (Cartesian index, coefficient)
     std::vector<int> ici(3 * S.nbf, -1);
     std::vector<double> icc(3 * S.nbf, 0.0);
@@ -325,6 +340,17 @@ int create_device(pbc_jk *h)
         for (int g = S.class_start[c]; g < S.class_start[c + 1]; ++g)
             h->class_max_pp[c] = std::max(h->class_max_pp[c], S.groups[g].pend - S.groups[g].pstart);
     }
+    // Hermite densities: n_h(l_a + l_b) values per pair, class by class (the
+    // pairs of a class are contiguous, in the order of its groups)
+    h->hd_base[0] = 0;
+    for (int c = 0; c < kNumClass; ++c) {
+        const int g0 = S.class_start[c], g1 = S.class_start[c + 1];
+        const int p0 = g0 < g1 ? S.groups[g0].pstart : 0, p1 = g0 < g1 ? S.groups[g1 - 1].pend : 0;
+        const int lab = kClassL[c];
+        h->class_p0[c] = p0;
+        h->hd_base[c + 1] = h->hd_base[c] + (long)(p1 - p0) * ((lab + 1) * (lab + 2) * (lab + 3) / 6);
+    }
+    if ((rc = dalloc(h, &h->d_hd, (size_t)std::max(1L, h->hd_base[kNumClass])))) return rc;
     if (!h->dry) {
         if (!h->h_cnt) HIPCHK(hipHostMalloc((void **)&h->h_cnt, kNumCounters * sizeof(unsigned long long)));
         if (!h->h_ctl) HIPCHK(hipHostMalloc((void **)&h->h_ctl, 4 * sizeof(int)));
@@ -337,6 +363,7 @@ int create_device(pbc_jk *h)
     }
     // reciprocal-space chunk: F and T hold 2 * gchunk matrices each
     if (const char *e = std::getenv("PBCJK_Y_TILE")) h->y_tile = std::atoi(e) == 128 ? 128 : 64;
+    if (const char *e = std::getenv("PBCJK_COOP_RATIO")) h->coop_ratio = std::max(0.0, std::atof(e));
     const int nG = (int)S.Gw.size();
     double budget_mb = h->lr_budget_mb > 0 ? h->lr_budget_mb : 16384.0;
     if (const char *e = std::getenv("PBCJK_LR_BUDGET_MB")) budget_mb = std::max(64.0, std::atof(e));
@@ -445,6 +472,7 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
     double *Jo = dJ ? dJ : h->d_Jo;
     double *Ko = dK ? dK : h->d_Ko;
     h->ntimed = 0;
+    h->stat_cnt = h->d_cnt;
     HIPCHK(hipEventRecord(h->ev[0], st));
 
     // B1: density in the scaled Cartesian basis, block maxima
@@ -464,7 +492,7 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
             const double nq = (double)h->h_cnt[24 + k], nt = (double)h->h_cnt[2 + k];
             if (nq > 0) {
                 h->fold[k] = nt > kFoldRatio * nq;
-                h->coop_d[k] = nt > kCoopRatio * nq;
+                h->coop_d[k] = nt > h->coop_ratio * nq;
             }
         }
 
@@ -476,7 +504,18 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
     // B3/B4: short-range J and K.  Per class pair: the density-weighted
     // screen compacts the neighbour list into FP64 and FP32 work lists, then
     // one launch per list.
-    h->st.sr_fold_mask = h->st.sr_kernel_mask = 0;
+    h->st.sr_fold_mask = h->st.sr_kernel_mask = h->st.sr_jengine_mask = 0;
+    // without K the J-engine runs: Hermite densities of every pair first (B2)
+    const bool jonly = !wantK;
+    if ((h->parts & PBC_JK_PART_SR) && jonly) {
+        for (int c = 0; c < kNumClass; ++c) {
+            HdensArgs ha{};
+            ha.pairs = h->d_pairs; ha.groups = h->d_groups;
+            ha.g0 = S.class_start[c]; ha.ngroups = S.class_start[c + 1] - S.class_start[c];
+            ha.p0 = h->class_p0[c]; ha.Dt = h->d_Dt; ha.nbfc = n; ha.hd = h->d_hd + h->hd_base[c];
+            HIPCHK(launch_hdens(c, ha, st));
+        }
+    }
     if (h->parts & PBC_JK_PART_SR) {
         HIPCHK(launch_fill((double *)h->d_wcnt, 42, 0.0, st));
         SRArgs a{};
@@ -515,6 +554,8 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
                 a.tri = (cb == ck);
                 a.max_entries = e1 - e0;
                 a.max_prim_pairs = std::max(h->class_max_pp[cb], h->class_max_pp[ck]);
+                a.hd_b = h->d_hd + h->hd_base[cb]; a.hd_p0b = h->class_p0[cb];
+                a.hd_k = h->d_hd + h->hd_base[ck]; a.hd_p0k = h->class_p0[ck];
                 for (int prec = 0; prec < (split ? 2 : 1); ++prec) {
                     a.nbr_bra = !split ? pa.bra : prec ? pa.b32 : pa.b64;
                     a.nbr_ket = !split ? pa.ket : prec ? pa.k32 : pa.k64;
@@ -525,7 +566,15 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
                     TimedLaunch tl(h, st, 5 + slot, 0.0);
                     if (h->fold[slot]) h->st.sr_fold_mask |= 1 << slot;
                     if (coop && (h->coop_d[slot] || !sr_sliceable(cb, ck))) h->st.sr_kernel_mask |= 1 << slot;
-                    hipError_t e;
+                    hipError_t e = hipErrorNotSupported;
+                    if (jonly) {
+                        e = launch_sr_j(cb, ck, a, st);
+                        if (e == hipSuccess) {
+                            h->st.sr_jengine_mask |= 1 << slot;
+                            continue;
+                        }
+                        if (e != hipErrorNotSupported) HIPCHK(e);
+                    }
                     if (!coop) e = launch_sr_jk(cb, ck, a, prec == 1, h->fold[slot], st);
                     else if (!h->coop_d[slot]) e = launch_sr_slices(cb, ck, a, h->fold[slot], st);
                     else e = hipErrorNotSupported;
@@ -778,7 +827,7 @@ int handle_new(const pbc_cell *cell, const pbc_atoms *atoms, const pbc_basis *ba
     std::string err;
     int rc;
     try {
-        rc = build_setup(cell->a, atoms->natom, atoms->xyz, basis->nshell, basis->atom, basis->l, basis->pure,
+        rc = build_setup(cell->a, atoms->natom, atoms->xyz, atoms->charge, basis->nshell, basis->atom, basis->l, basis->pure,
                          basis->nprim, basis->exps, basis->coefs, omega, th, h->S, err);
     } catch (const std::bad_alloc &) {
         delete h;
@@ -893,6 +942,96 @@ int pbc_jk_build_device(pbc_jk *h, const double *dD, double *dJ, double *dK, dou
     return rc;
 }
 
+int pbc_jk_one_electron(pbc_jk *h, double *S_out, double *T_out, double *V_out, double *E_nuc)
+{
+    g_err.clear();
+    if (!h) return fail(PBC_JK_EINVAL, "handle is NULL");
+    const Setup &S = h->S;
+    const bool wantV = V_out || E_nuc;
+    if (wantV && S.charge.empty())
+        return fail(PBC_JK_EINVAL, "the nuclear attraction and E_nuc need the atom charges (pbc_atoms.charge)");
+    HIPCHK(hipSetDevice(h->device));
+    hipStream_t st = h->own;
+    const int n = S.nbfc, nb = S.nbf;
+    const long n2 = (long)n * n, m2 = (long)nb * nb;
+    // halves of S, T and V in X, Y, Jt; the reciprocal part and self term of V in Kt
+    HIPCHK(launch_fill(h->d_X, n2, 0.0, st));
+    HIPCHK(launch_fill(h->d_Y, n2, 0.0, st));
+    HIPCHK(launch_fill(h->d_Jt, n2, 0.0, st));
+    HIPCHK(launch_fill(h->d_Kt, n2, 0.0, st));
+    HIPCHK(launch_fill(h->d_scal, 4, 0.0, st));
+    for (int c = 0; c < kNumClass; ++c) {
+        OneEArgs oa{};
+        oa.pairs = h->d_pairs; oa.groups = h->d_groups;
+        oa.g0 = S.class_start[c]; oa.ngroups = S.class_start[c + 1] - S.class_start[c];
+        oa.nbfc = n; oa.xyz = h->d_xyz; oa.q = h->d_q; oa.natom = wantV ? S.natom : 0;
+        oa.lat = lat_args(S); oa.w2 = S.omega * S.omega; oa.d_ewald_R = S.d_ewald_R;
+        oa.rcap2 = S.r_cut > 0 ? S.r_cut * S.r_cut : 0.0;
+        oa.boys = h->d_boys; oa.bexp = h->d_bexp;
+        oa.XS = h->d_X; oa.XT = h->d_Y; oa.XV = h->d_Jt;
+        HIPCHK(launch_one_e(c, oa, st));
+    }
+    double e_self = 0.0;
+    if (wantV) {
+        // reciprocal part: the pair structure factors against rho_n(G)
+        const int nG = (int)S.Gw.size();
+        SfacArgs sa{};
+        sa.pairs = h->d_pairs; sa.sp_start = h->d_sp_start; sa.sp_pairs = h->d_sp_pairs;
+        sa.sp_shA = h->d_sp_shA; sa.sp_shB = h->d_sp_shB; sa.sh_l = h->d_sh_l; sa.sh_aoc = h->d_sh_aoc;
+        sa.F = h->d_F; sa.nbfc = n;
+        for (int g0 = 0; g0 < nG; g0 += h->gchunk) {
+            const int gc = std::min(h->gchunk, nG - g0);
+            sa.G = h->d_G + 3 * g0; sa.Gs = h->d_Gs + g0; sa.ng = gc;
+            HIPCHK(launch_fill(h->d_F, 2L * gc * n2, 0.0, st));
+            for (int c = 0; c < kNumClass; ++c) {
+                sa.sp0 = S.sp_class_start[c];
+                sa.nsp = S.sp_class_start[c + 1] - S.sp_class_start[c];
+                HIPCHK(launch_sfac(c, sa, st));
+            }
+            HIPCHK(launch_rho_nuc(h->d_G + 3 * g0, h->d_Gs + g0, gc, h->d_xyz, h->d_q, S.natom, h->d_rho, st));
+            HIPCHK(launch_jlr(h->d_F, h->d_rho, nullptr, gc, (int)n2, h->d_Kt, st));
+            // E_nuc: 1/2 sum over the half space of |sqrt(W) rho_n|^2
+            HIPCHK(launch_dot(h->d_rho, h->d_rho, 2L * gc, h->d_scal + 1, st));
+        }
+        // self term -(pi/(V w^2)) sum_C q_C S
+        double qsum = 0.0, q2 = 0.0;
+        for (double z : S.charge) { qsum -= z; q2 += z * z; }
+        const double f = -kPi / (S.lat.V * S.omega * S.omega);
+        HIPCHK(launch_fill(h->d_scal, 1, qsum, st));
+        HIPCHK(launch_axpy_scaled(h->d_Kt, h->d_S, n2, f, h->d_scal, st));
+        // E_nuc real space: radius from erfc(x) < (2/sqrt(pi)) e^{-x^2}/x,
+        // (2/sqrt(pi)) e^{-w^2 r^2}/(w r^2) = delta_EwaldR
+        const double w = S.omega;
+        auto tail = [&](double r) { return 2.0 / std::sqrt(kPi) * std::exp(-w * w * r * r) / (w * r * r); };
+        double lo = 1e-3, hi = 1.0;
+        while (tail(hi) > S.d_ewald_R) hi *= 2.0;
+        for (int it = 0; it < 200; ++it) {
+            const double m = 0.5 * (lo + hi);
+            (tail(m) > S.d_ewald_R ? lo : hi) = m;
+        }
+        HIPCHK(launch_enuc_real(h->d_xyz, h->d_q, S.natom, lat_args(S), w, hi * hi, h->d_scal + 2, st));
+        // self and neutralising-background terms of the point charges
+        e_self = -w / std::sqrt(kPi) * q2 - kPi / (2.0 * S.lat.V * w * w) * qsum * qsum;
+    }
+    double *outs[3] = {S_out, T_out, V_out};
+    const double *halves[3] = {h->d_X, h->d_Y, h->d_Jt};
+    for (int k = 0; k < 3; ++k) {
+        if (!outs[k]) continue;
+        FinalArgs fa{halves[k], k == 2 ? h->d_Kt : nullptr, n, nb, 0, h->d_inv_ci, h->d_inv_cc, h->d_Jo};
+        HIPCHK(launch_final(fa, st));
+        HIPCHK(hipMemcpyAsync(outs[k], h->d_Jo, m2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    if (E_nuc) {
+        double e[2];
+        HIPCHK(hipMemcpyAsync(e, h->d_scal + 1, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        *E_nuc = 0.5 * e[0] + e[1] + e_self;
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    return 0;
+}
+
 int pbc_jk_build(pbc_jk *h, const double *D, double *J, double *K, double *E_J, double *E_K)
 {
     g_err.clear();
@@ -971,7 +1110,7 @@ int pbc_jk_stats(const pbc_jk *hc, pbc_jk_counters *out)
         HIPCHK(hipEventElapsedTime(&c, h->ev[2], h->ev[3]));
         h->st.t_sr_ms = a; h->st.t_lr_ms = b; h->st.t_other_ms = c;
         unsigned long long cnt[kNumCounters];
-        HIPCHK(hipMemcpy(cnt, h->d_cnt, sizeof cnt, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(cnt, h->stat_cnt ? h->stat_cnt : h->d_cnt, sizeof cnt, hipMemcpyDeviceToHost));
         h->st.quartets = (double)cnt[0];
         h->st.terms = (double)cnt[1];
         h->st.terms_fp32 = (double)cnt[23];

@@ -34,7 +34,7 @@ struct alignas(32) PairRec {
     double Q;       // short-range Cauchy-Schwarz factor: sqrt of the largest normalised
                     // component of the pair's (ab|ab) with the erfc kernel
     double Cb;      // |Ca Cb| K without the symmetry weight (real-space sphere bound)
-    double pad[3];   // pad[0] = 1/p
+    double pad[3];   // pad[0] = 1/p, pad[1] = b (exponent of the second primitive)
 };
 
 // A group: one (first shell, second shell, image) with its primitive pairs.
@@ -74,6 +74,7 @@ struct Setup {
     int nshell = 0, nbf = 0, nbfc = 0, natom = 0;
     std::vector<int> sh_l, sh_pure, sh_atom, sh_aoc, sh_ao, sh_nprim;
     std::vector<double> xyz;
+    std::vector<double> charge;    // nuclear charges Z (empty when none were given)
     // Output transform: for each scaled-Cartesian AO i, up to two
     // (output AO, coefficient) entries: J_out = T' J~ T'^T with T' = T diag(rho).
     std::vector<int> tr_ao;        // 2 * nbfc
@@ -96,7 +97,7 @@ struct Setup {
 };
 
 // setup.cpp
-int build_setup(const double *cell, int natom, const double *xyz, int nshell, const int *atom,
+int build_setup(const double *cell, int natom, const double *xyz, const double *charge, int nshell, const int *atom,
                 const int *l, const int *pure, const int *nprim, const double *exps,
                 const double *coefs, double omega, const double thr[8], Setup &S,
                 std::string &err);

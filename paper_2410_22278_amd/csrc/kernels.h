@@ -30,7 +30,27 @@ struct SRArgs {
                                     // [2 + slot] terms of this class pair, [23] FP32 terms,
                                     // [24 + slot] primitive quartets of this class pair
     int slot;             // class-pair index (0..20)
+    // J-engine only: Hermite densities of the bra and ket classes' pairs, the
+    // densities of pair k at hd + (k - hd_p0) n_h(l_a + l_b)
+    const double *hd_b, *hd_k;
+    int hd_p0b, hd_p0k;
 };
+
+// Hermite densities of one class's primitive pairs (B2 of the J-engine):
+// hd[(k - p0) n_h + h] = cpre_k sum_{a,b} E^{ab}_h(k) Dt[a][b] for the pairs k
+// of groups g0 .. g0 + ngroups - 1 (pairs p0 onwards).
+struct HdensArgs {
+    const PairRec *pairs;
+    const GroupRec *groups;
+    int g0, ngroups, p0;
+    const double *Dt;
+    int nbfc;
+    double *hd;
+};
+hipError_t launch_hdens(int cls, const HdensArgs &a, hipStream_t st);
+// Short-range J alone (J-engine) of class pair (cb, ck); hipErrorNotSupported
+// for the class pairs it does not cover (total angular momentum above 5).
+hipError_t launch_sr_j(int cb, int ck, const SRArgs &a, hipStream_t st);
 
 // Neighbour list of one class pair: every (bra group, ket group) that has at
 // least one real-space term for some density (mode 0 counts per bra, mode 1
@@ -73,6 +93,32 @@ hipError_t launch_sr_slices(int cb, int ck, const SRArgs &a, bool fold, hipStrea
 hipError_t launch_sr_slices_dp(int cb, int ck, const SRArgs &a, bool fold, hipStream_t st);
 // class pairs with total angular momentum >= 5 (one wavefront per group pair)
 hipError_t launch_sr_coop(int cb, int ck, const SRArgs &a, hipStream_t st);
+
+// ---- one-electron terms (one_e.hip)
+
+// S, T and the short-range part of V of the pairs of one class's groups, into
+// halves in the scaled Cartesian basis (M = X + X^T).
+struct OneEArgs {
+    const PairRec *pairs;
+    const GroupRec *groups;
+    int g0, ngroups;
+    int nbfc;
+    const double *xyz, *q;   // natom positions, point charges (potential q_C / |r - C|)
+    int natom;
+    LatArgs lat;
+    double w2, d_ewald_R, rcap2;
+    const double *boys, *bexp;
+    double *XS, *XT, *XV;
+};
+hipError_t launch_one_e(int cls, const OneEArgs &a, hipStream_t st);
+// Nuclear structure factor on ng half-space vectors, scaled by Gs: rho[g] real
+// parts, rho[ng + g] imaginary parts of sum_C q_C e^{-i G.C}.
+hipError_t launch_rho_nuc(const double *G, const double *Gs, int ng, const double *xyz, const double *q, int natom,
+                          double *rho, hipStream_t st);
+// *out += real-space part of the point-charge Ewald energy (images within
+// sqrt(rb2) of each atom pair).
+hipError_t launch_enuc_real(const double *xyz, const double *q, int natom, const LatArgs &lat, double w,
+                            double rb2, double *out, hipStream_t st);
 
 // ---- long range and utilities (lr.hip)
 
@@ -177,7 +223,7 @@ hipError_t launch_axpy_scaled(double *Y, const double *X, long n, double f, cons
 // Finalise: Jc = X + X^T + Jt, out[a][b] = sum T'[a][i] T'[b][j] Jc[i][j]
 // using the inverse transform lists (up to 3 entries per output AO).
 struct FinalArgs {
-    const double *X, *Jt;
+    const double *X, *Jt;  // Jt may be NULL (no full-matrix part)
     int nbfc, nbf;
     int jt_block;          // > 0: Jt holds only its upper blocks of this size (block row <= block column); 0: whole
     const int *inv_ci;     // 3 * nbf scaled-Cartesian indices (-1 = none)

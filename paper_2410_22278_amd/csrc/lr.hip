@@ -148,14 +148,18 @@ __device__ __forceinline__ double block_sum(double v, double *sh)
     return t;
 }
 
+// rho[b] += sum_i F[b][i] Dt[i]: blockIdx.y = b, blockIdx.x = slice of the
+// matrix (enough blocks per matrix to stream it at full bandwidth); rho must
+// be zero on entry.
 __global__ __launch_bounds__(256) void k_dot_batched(const double *F, const double *Dt, long n2, double *rho)
 {
     __shared__ double sh[4];
-    const double *f = F + (long)blockIdx.x * n2;
+    const double *f = F + (long)blockIdx.y * n2;
     double s = 0.0;
-    for (long i = threadIdx.x; i < n2; i += blockDim.x) s += f[i] * Dt[i];
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += (long)gridDim.x * blockDim.x)
+        s += f[i] * Dt[i];
     double t = block_sum(s, sh);
-    if (threadIdx.x == 0) rho[blockIdx.x] = t;
+    if (threadIdx.x == 0) atomicAdd(&rho[blockIdx.y], t);
 }
 
 __global__ __launch_bounds__(256) void k_dot(const double *A, const double *B, long n, double *out)
@@ -264,7 +268,7 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs a)
             if (j < 0) continue;
             long jt = (long)i * nc + j;
             if (a.jt_block > 0 && i / a.jt_block > j / a.jt_block) jt = (long)j * nc + i;
-            double x = a.X[(long)i * nc + j] + a.X[(long)j * nc + i] + a.Jt[jt];
+            double x = a.X[(long)i * nc + j] + a.X[(long)j * nc + i] + (a.Jt ? a.Jt[jt] : 0.0);
             s += a.inv_cc[3 * p + u] * a.inv_cc[3 * q + v] * x;
         }
     }
@@ -720,7 +724,11 @@ hipError_t launch_sfac(int cls, const SfacArgs &a, hipStream_t st)
 hipError_t launch_dot_batched(const double *F, const double *Dt, int n2, int nb, double *rho, hipStream_t st)
 {
     if (nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_dot_batched, dim3(nb), dim3(256), 0, st, F, Dt, (long)n2, rho);
+    hipError_t e = launch_fill(rho, nb, 0.0, st);
+    if (e != hipSuccess) return e;
+    // about 2048 blocks in all, at most one per 256 x 16 elements of a matrix
+    const long per = std::max(1L, std::min<long>((n2 + 4095) / 4096, (2048 + nb - 1) / nb));
+    hipLaunchKernelGGL(k_dot_batched, dim3((unsigned)per, nb), dim3(256), 0, st, F, Dt, (long)n2, rho);
     return hipGetLastError();
 }
 
@@ -741,17 +749,18 @@ hipError_t launch_jlr(const double *F, const double *rho, const double *Gw, int 
     return hipGetLastError();
 }
 
-// Workgroups of the persistent GEMM grid: enough to keep every CU busy with
-// several resident workgroups, few enough that a launch gated off on the
-// device costs little.
-constexpr long kGemmGrid = 2048;
+// Workgroups of the persistent grid of device-gated products.
+constexpr long kGemmGrid = 1024;
 
 template <int T>
 hipError_t launch_dgemm_t(const GemmArgs &a, hipStream_t st)
 {
     const long z = a.reduce ? a.slices : a.nbatch;
     const long tiles = (long)((a.N + T - 1) / T) * ((a.M + T - 1) / T) * z;
-    dim3 grid((unsigned)std::min(tiles, kGemmGrid));
+    // one tile per workgroup, except for products that run only when the
+    // device-side decision falls back to them: a capped persistent grid, so
+    // that the usual case (gated off) costs few workgroups
+    dim3 grid((unsigned)(a.ctl_mode == 3 ? std::min(tiles, kGemmGrid) : tiles));
     switch (a.role) {
         case 1: hipLaunchKernelGGL((k_dgemm<1, T>), grid, dim3(256), 0, st, a); break;
         case 2: hipLaunchKernelGGL((k_dgemm<2, T>), grid, dim3(256), 0, st, a); break;

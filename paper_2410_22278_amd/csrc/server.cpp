@@ -403,8 +403,13 @@ void worker(pbc_jk_server *s)
         cell->last_use = ++s->tick;
         if (!s->cfg.cache_cells || rc == PBC_JK_EDEVICE) {
             s->cells.erase(r->in.sig);
-            to_delete.push_back(cell->h);
+            pbc_jk *drop = cell->h;
             delete cell;
+            // the cell's memory goes back to the arena before the request
+            // completes, so that a completed request holds no arena bytes
+            lk.unlock();
+            handle_delete(drop);
+            lk.lock();
         }
         finish(s, r, rc, msg);
         s->cv_work.notify_all();

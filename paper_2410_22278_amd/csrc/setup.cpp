@@ -209,7 +209,7 @@ void boys_table(std::vector<double> &tab)
     }
 }
 
-int build_setup(const double *cell, int natom, const double *xyz, int nshell, const int *atom,
+int build_setup(const double *cell, int natom, const double *xyz, const double *charge, int nshell, const int *atom,
                 const int *l, const int *pure, const int *nprim, const double *exps,
                 const double *coefs, double omega, const double thr[8], Setup &S, std::string &err)
 {
@@ -235,6 +235,12 @@ int build_setup(const double *cell, int natom, const double *xyz, int nshell, co
 
     S.natom = natom;
     S.xyz.assign(xyz, xyz + 3 * natom);
+    S.charge.clear();
+    if (charge) {
+        for (int i = 0; i < natom; ++i)
+            if (!finite(charge[i])) { err = "atom charge is not finite"; return -1; }
+        S.charge.assign(charge, charge + natom);
+    }
     S.nshell = nshell;
     S.sh_l.resize(nshell); S.sh_pure.resize(nshell); S.sh_atom.resize(nshell);
     S.sh_aoc.resize(nshell); S.sh_ao.resize(nshell); S.sh_nprim.resize(nshell);
@@ -365,7 +371,8 @@ int build_setup(const double *cell, int natom, const double *xyz, int nshell, co
                                   std::sqrt(sr_self_max(la, lb, a, b, pa, pb, S.omega));
                         t.rec.Cb = Cab * g;
                         t.rec.pad[0] = 1.0 / p;
-                        t.rec.pad[1] = t.rec.pad[2] = 0.0;
+                        t.rec.pad[1] = b;
+                        t.rec.pad[2] = 0.0;
                         // Separable real-space bound: C2e (1 - c) <= Z_bra Z_ket, using
                         // 2pi^{5/2}/(pq sqrt(p+q)) <= prod sqrt2 pi^{5/4}/(p (p+2amin)^{1/4})
                         // and 1 - w/sqrt(rho+w^2) <= sqrt(prod (1 - w/sqrt(p+w^2))).

@@ -26,7 +26,8 @@ PART_SR, PART_LR, PART_SELF = 1, 2, 4
 LR_AUTO, LR_DENSE = 0, 1
 
 # every symbol the header declares
-EXPORTS = ["pbc_jk_create", "pbc_jk_build", "pbc_jk_build_device", "pbc_jk_destroy",
+EXPORTS = ["pbc_jk_create", "pbc_jk_build", "pbc_jk_build_device",
+           "pbc_jk_one_electron", "pbc_jk_destroy",
            "pbc_jk_nbf", "pbc_jk_stats", "pbc_jk_set_parts", "pbc_jk_set_sr_classes", "pbc_jk_set_lr", "pbc_jk_last_error",
            "pbc_jk_server_create", "pbc_jk_server_submit", "pbc_jk_server_wait", "pbc_jk_server_cancel",
            "pbc_jk_server_stats", "pbc_jk_server_destroy"]
@@ -62,7 +63,7 @@ class pbc_jk_counters(ctypes.Structure):
                 ("n_group_pairs", c_double), ("lr_rank", c_double), ("t_chol_ms", c_double),
                 ("gemm_kernel", c_int), ("t_sr_class_ms", c_double * 21), ("t_y_ms", c_double),
                 ("y_flops", c_double), ("n_y", c_int), ("sr_fold_mask", c_int),
-                ("sr_kernel_mask", c_int)]
+                ("sr_kernel_mask", c_int), ("sr_jengine_mask", c_int)]
 
 
 class pbc_jk_server_config(ctypes.Structure):
@@ -109,6 +110,9 @@ def load():
     lib.pbc_jk_build_device.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_double),
                                         POINTER(c_double), c_void_p]
     lib.pbc_jk_build_device.restype = c_int
+    lib.pbc_jk_one_electron.argtypes = [c_void_p, POINTER(c_double), POINTER(c_double), POINTER(c_double),
+                                        POINTER(c_double)]
+    lib.pbc_jk_one_electron.restype = c_int
     lib.pbc_jk_destroy.argtypes = [c_void_p]
     lib.pbc_jk_destroy.restype = None
     lib.pbc_jk_nbf.argtypes = [c_void_p]
@@ -159,7 +163,7 @@ def _ip(a):
     return a.ctypes.data_as(POINTER(c_int))
 
 
-def _inputs(cell, xyz, shell_atom, shell_l, shell_pure, shell_nprim, exps, coefs, thr):
+def _inputs(cell, xyz, shell_atom, shell_l, shell_pure, shell_nprim, exps, coefs, thr, charge=None):
     """C structs for one cell; `keep` owns the arrays the structs point into."""
     c = pbc_cell()
     c.a[:] = [float(x) for x in np.asarray(cell, dtype=np.float64).ravel()]
@@ -170,7 +174,9 @@ def _inputs(cell, xyz, shell_atom, shell_l, shell_pure, shell_nprim, exps, coefs
             np.ascontiguousarray(shell_nprim, dtype=np.int32),
             np.ascontiguousarray(exps, dtype=np.float64),
             np.ascontiguousarray(coefs, dtype=np.float64)]
-    at = pbc_atoms(keep[0].shape[0], _dp(keep[0]), None)
+    if charge is not None:
+        keep.append(np.ascontiguousarray(charge, dtype=np.float64))
+    at = pbc_atoms(keep[0].shape[0], _dp(keep[0]), _dp(keep[7]) if len(keep) > 7 else None)
     bs = pbc_basis(keep[1].shape[0], _ip(keep[1]), _ip(keep[2]), _ip(keep[3]), _ip(keep[4]),
                    _dp(keep[5]), _dp(keep[6]))
     th = None
@@ -181,10 +187,11 @@ def _inputs(cell, xyz, shell_atom, shell_l, shell_pure, shell_nprim, exps, coefs
 
 
 def pbc_jk_create(cell, xyz, shell_atom, shell_l, shell_pure, shell_nprim, exps, coefs,
-                  omega: float, thr=None) -> int:
+                  omega: float, thr=None, charge=None) -> int:
     """Returns the opaque handle (an integer address)."""
     lib = load()
-    c, at, bs, th, keep = _inputs(cell, xyz, shell_atom, shell_l, shell_pure, shell_nprim, exps, coefs, thr)
+    c, at, bs, th, keep = _inputs(cell, xyz, shell_atom, shell_l, shell_pure, shell_nprim, exps, coefs, thr,
+                                  charge)
     h = c_void_p()
     rc = lib.pbc_jk_create(byref(c), byref(at), byref(bs), float(omega),
                            byref(th) if th is not None else None, byref(h))
@@ -207,10 +214,11 @@ def pbc_jk_build(h: int, D, want_J: bool = True, want_K: bool = True):
     J = np.empty((n, n)) if want_J else None
     K = np.empty((n, n)) if want_K else None
     ej, ek = c_double(), c_double()
+    # E_K is asked for only with K: without it the library runs the J-engine
     rc = lib.pbc_jk_build(c_void_p(h), _dp(D), _dp(J) if J is not None else None,
-                          _dp(K) if K is not None else None, byref(ej), byref(ek))
+                          _dp(K) if K is not None else None, byref(ej), byref(ek) if want_K else None)
     _check(rc)
-    return J, K, ej.value, ek.value
+    return J, K, ej.value, (ek.value if want_K else None)
 
 
 def _stream_ptr(stream):
@@ -237,17 +245,35 @@ def _check_device_buffers(h: int, **bufs):
 def pbc_jk_build_device(h: int, dD, dJ=None, dK=None, energies: bool = True, stream=None):
     """Device-memory build on torch tensors (float64, cuda, contiguous,
     nbf x nbf), queued on `stream` (default: torch's current stream).
-    Returns (E_J, E_K) when energies, else None (asynchronous)."""
+    Returns (E_J, E_K) when energies (E_K None without dK: a J-only build
+    runs the J-engine), else None (asynchronous)."""
     lib = load()
     _check_device_buffers(h, dD=dD, dJ=dJ, dK=dK)
     ej, ek = c_double(), c_double()
+    want_ek = energies and dK is not None
     rc = lib.pbc_jk_build_device(c_void_p(h), c_void_p(dD.data_ptr()),
                                  c_void_p(dJ.data_ptr()) if dJ is not None else None,
                                  c_void_p(dK.data_ptr()) if dK is not None else None,
-                                 byref(ej) if energies else None, byref(ek) if energies else None,
+                                 byref(ej) if energies else None, byref(ek) if want_ek else None,
                                  _stream_ptr(stream))
     _check(rc)
-    return (ej.value, ek.value) if energies else None
+    return (ej.value, ek.value if want_ek else None) if energies else None
+
+
+def pbc_jk_one_electron(h: int, want_S=True, want_T=True, want_V=True, want_E_nuc=True):
+    """Returns (S, T, V, E_nuc) of the handle's cell (None for what was not
+    asked for)."""
+    lib = load()
+    n = pbc_jk_nbf(h)
+    _check(n if n < 0 else 0)
+    S = np.empty((n, n)) if want_S else None
+    T = np.empty((n, n)) if want_T else None
+    V = np.empty((n, n)) if want_V else None
+    e = c_double()
+    rc = lib.pbc_jk_one_electron(c_void_p(h), _dp(S) if S is not None else None, _dp(T) if T is not None else None,
+                                 _dp(V) if V is not None else None, byref(e) if want_E_nuc else None)
+    _check(rc)
+    return S, T, V, (e.value if want_E_nuc else None)
 
 
 def pbc_jk_destroy(h: int):
@@ -283,7 +309,7 @@ class Handle:
         t = thr if thr is not None else system.thr
         self.h = pbc_jk_create(system.cell, system.xyz, system.shell_atom, system.shell_l,
                                system.shell_pure, system.shell_nprim, system.exps, system.coefs,
-                               system.omega if omega is None else omega, t)
+                               system.omega if omega is None else omega, t, getattr(system, "charge", None))
         self.nbf = pbc_jk_nbf(self.h)
 
     def build(self, D, want_J=True, want_K=True):
@@ -294,6 +320,9 @@ class Handle:
 
     def stats(self):
         return pbc_jk_stats(self.h)
+
+    def one_electron(self, **kw):
+        return pbc_jk_one_electron(self.h, **kw)
 
     def set_parts(self, mask):
         pbc_jk_set_parts(self.h, mask)

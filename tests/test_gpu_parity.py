@@ -233,3 +233,52 @@ def test_d_kernel_choice_over_builds(lib, oracle_mod):
             ratio = st["terms"] / max(1.0, st["quartets"])
             dJ, dK, dEJ, dEK = _report(f"d build {k} (shifts/quartet {ratio:.1f})", J, K, ref, s.natom, EJ, EK)
             assert dJ < 1e-9 and dK < 1e-9 and dEJ < 1e-9 and dEK < 1e-9
+
+
+# ---------------------------------------------------------------- J-engine (builds without K)
+
+J_CASES = [dict(seed=3, natom=2, recipe=((0, 0), (1, 0))),
+           dict(seed=5, natom=3, recipe=((0, 0), (0, 0), (1, 0)), skew=0.15, omega=0.35),
+           D_CASES[0], D_CASES[1]]
+
+
+@pytest.mark.parametrize("case", J_CASES, ids=["sp", "sp_skewed", "spd_spherical", "pd_cartesian_skewed"])
+def test_j_only_engine(lib, oracle_mod, case):
+    """Without K the short range runs the J-engine (Hermite densities of the
+    pairs, Sec. 3.2): J against the oracle's J at the FP64 bar, and the
+    counters show which class pairs it ran (total angular momentum <= 5)."""
+    s = inputs.small_cell(**case)
+    ref = oracle_mod.jk(s)
+    with lib.Handle(s) as h:
+        J, K, EJ, EK = h.build(s.D, want_K=False)
+        st = h.stats()
+    assert K is None and EK is None
+    dJ = np.abs(J - ref["J"]).max()
+    dEJ = abs(EJ - ref["E_J"]) / s.natom
+    print(f"J-only {s.name}: max|dJ|={dJ:.3e} dE_J/atom={dEJ:.3e} jengine mask {st['sr_jengine_mask']:#x}",
+          flush=True)
+    assert dJ < 1e-9 and dEJ < 1e-9
+    assert st["sr_jengine_mask"] != 0
+
+
+def test_j_only_cfg1_and_cfg2_rows(lib, oracle_mod):
+    s1 = inputs.cfg1()
+    ref1 = oracle_mod.jk(s1)
+    with lib.Handle(s1) as h:
+        J1, _, EJ1, _ = h.build(s1.D, want_K=False)
+    d1 = np.abs(J1 - ref1["J"]).max()
+    s2 = inputs.cfg2()
+    shells = [0, 3, 7]
+    ref2 = oracle_mod.jk(s2, bra_shells=shells)
+    rows = ref2["rows"]
+    with lib.Handle(s2) as h:
+        J2, _, _, _ = h.build(s2.D, want_K=False)
+        st = h.stats()
+    d2 = np.abs(J2[rows] - ref2["J"][rows]).max()
+    print(f"J-only cfg1 max|dJ|={d1:.3e} dE_J={EJ1 - ref1['E_J']:.3e}; cfg2 rows max|dJ|={d2:.3e}, "
+          f"short range {st['t_sr_ms']:.1f} ms, build {st['t_build_ms']:.1f} ms", flush=True)
+    assert d1 < 1e-9 and abs(EJ1 - ref1["E_J"]) < 1e-9 and d2 < 1e-9
+    # every class pair of the s/p cell ran the J-engine
+    for k in range(21):
+        if st["terms_class"][k] > 0:
+            assert (st["sr_jengine_mask"] >> k) & 1, k

@@ -141,3 +141,31 @@ def test_cancel_and_bad_request_isolation(lib, alone):
     assert r3["status"] == lib.PBC_JK_EINVAL
     _same("after bad request", r4, alone[4])
     assert st["failed"] == 1
+
+
+@pytest.mark.parametrize("cache", [False, True], ids=["no_cache", "cache"])
+def test_cancel_second_request_of_same_cell(lib, alone, cache):
+    """Two requests for the same cell (the second with another density) on a
+    one-slot server, the second cancelled while the first is queued or its
+    cell is being created: the first keeps its cell and completes with the
+    alone result, and a third request for the cell still runs."""
+    s = alone[2][0]
+    D2 = 0.5 * s.D
+    with lib.Server(slots=1, cache_cells=cache) as srv:
+        t1 = srv.submit(s)
+        t2 = srv.submit(s, D=D2)
+        rc = srv.cancel(t2)
+        r1 = srv.wait(t1)
+        r2 = srv.wait(t2)
+        r3 = srv.wait(srv.submit(s))
+        st = srv.stats()
+    print(f"same-cell cancel (cache={cache}): rc={rc} -> {r2['status']}; stats {st}", flush=True)
+    _same("same cell, first", r1, alone[2])
+    _same("same cell, after the cancel", r3, alone[2])
+    if rc == 0:
+        assert r2["status"] == lib.PBC_JK_ECANCELED
+    else:
+        assert rc == lib.PBC_JK_EBUSY and r2["status"] == 0
+    assert st["failed"] == 0
+    if not cache:
+        assert st["in_use"] == 0
