@@ -188,6 +188,24 @@ int pbc_jk_build(pbc_jk *h, const double *D, double *J, double *K, double *E_J, 
 int pbc_jk_build_device(pbc_jk *h, const double *dD, double *dJ, double *dK,
                         double *E_J, double *E_K, void *stream);
 
+/* The same build as pbc_jk_build_device without any device allocation,
+ * for callers that cannot allocate (code under stream capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the per-build work buffers
+ * (densities and J/K halves in the scaled Cartesian basis, the reciprocal
+ * structure-factor chunk and products, the density factor, counters) come
+ * from one static device array of 256 MiB per GPU, held until the process
+ * ends; the handle keeps only its setup data and neighbour lists in use.
+ * The reciprocal chunk is shrunk to fit; a cell whose work buffers do not
+ * fit even with one reciprocal vector per chunk (about 94 nbf_cart^2 bytes:
+ * nbf_cart up to about 1600) fails with PBC_JK_ENOMEM.  The call allocates
+ * nothing: no hipMalloc, hipFree or allocating library routine.  Every call
+ * on one GPU shares that GPU's array: calls whose work overlaps on the device
+ * (two streams, two threads) race and give wrong results; calls queued on
+ * one stream are ordered.  The counters of pbc_jk_stats then describe this
+ * build.  Arguments, stream ordering and errors as pbc_jk_build_device. */
+int pbc_jk_build_device_static(pbc_jk *h, const double *dD, double *dJ, double *dK,
+                               double *E_J, double *E_K, void *stream);
+
 /* Gamma-point one-electron terms on the handle's pair list, lattice and
  * reciprocal vectors (host outputs, nbf x nbf, each may be NULL):
  *   S     overlap (Sec. 2.2, eq. pbc_overlap_formula);

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -81,7 +82,7 @@ struct pbc_jk {
     double *d_Jt = nullptr, *d_Kt = nullptr, *d_F = nullptr, *d_T = nullptr, *d_rho = nullptr;
     double *d_scal = nullptr, *d_Jo = nullptr, *d_Ko = nullptr;
     unsigned long long *d_dmaxg = nullptr, *d_cnt = nullptr;
-    unsigned long long *stat_cnt = nullptr;   // counters of the last build
+    unsigned long long *stat_cnt = nullptr;   // counters of the last build (own or scratch buffer)
     // J-engine: Hermite densities of every primitive pair (per class, pairs
     // p0 .. of the class at hd + hd_base[class])
     double *d_hd = nullptr;
@@ -903,6 +904,104 @@ void handle_delete(pbc_jk *h)
 
 }  // namespace pbcjk
 
+namespace {
+
+// ---------------------------------------------------------------- allocation-free build
+// Work buffers of pbc_jk_build_device_static: one file-scope device array
+// per GPU (held until the process ends), carved per call.  Host code never
+// uses the array's name as an address: the device address comes from
+// hipGetSymbolAddress, once per device, with that device current.
+constexpr size_t kScratchBytes = size_t(256) << 20;
+constexpr int kScratchDevices = 64;
+__device__ __align__(256) char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kScratchDevices] = {};
+
+int scratch_address(int dev, char **out)
+{
+    if (dev < 0 || dev >= kScratchDevices) return fail(PBC_JK_ENOTSUP, "device index above the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(PBC_JK_EDEVICE, "hipGetSymbolAddress returned no address for the scratch array");
+        g_scratch_ptr[dev] = (char *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return 0;
+}
+
+// The per-build work buffers of a handle (the setup data, the neighbour
+// lists and their per-build work lists stay with the handle).
+struct WorkBufs {
+    double *D, *Dt, *Dmax, *X, *Y, *Jt, *Kt, *Jo, *Ko, *F, *T, *rho, *scal, *L, *pw, *hd;
+    unsigned long long *dmaxg, *cnt, *wcnt;
+    int *pwi, *ctl;
+    int gchunk;
+};
+
+WorkBufs work_of(const pbc_jk *h)
+{
+    return WorkBufs{h->d_D, h->d_Dt, h->d_Dmax, h->d_X, h->d_Y, h->d_Jt, h->d_Kt, h->d_Jo, h->d_Ko, h->d_F,
+                    h->d_T, h->d_rho, h->d_scal, h->d_L, h->d_pw, h->d_hd, h->d_dmaxg, h->d_cnt, h->d_wcnt,
+                    h->d_pwi, h->d_ctl, h->gchunk};
+}
+
+void set_work(pbc_jk *h, const WorkBufs &w)
+{
+    h->d_D = w.D; h->d_Dt = w.Dt; h->d_Dmax = w.Dmax; h->d_X = w.X; h->d_Y = w.Y; h->d_Jt = w.Jt;
+    h->d_Kt = w.Kt; h->d_Jo = w.Jo; h->d_Ko = w.Ko; h->d_F = w.F; h->d_T = w.T; h->d_rho = w.rho;
+    h->d_scal = w.scal; h->d_L = w.L; h->d_pw = w.pw; h->d_hd = w.hd; h->d_dmaxg = w.dmaxg; h->d_cnt = w.cnt;
+    h->d_wcnt = w.wcnt; h->d_pwi = w.pwi; h->d_ctl = w.ctl; h->gchunk = w.gchunk;
+}
+
+// Carves the work buffers out of [base, base + cap) with the largest
+// reciprocal chunk (at most the handle's own) that fits; ENOMEM if even one
+// reciprocal vector per chunk does not fit.
+int carve_work(const pbc_jk *h, char *base, size_t cap, WorkBufs &w)
+{
+    const Setup &S = h->S;
+    const size_t n = S.nbfc, n2 = n * n, m2 = (size_t)S.nbf * S.nbf, nblk = (n + 63) / 64;
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *p = base + off;
+        off += (bytes + 255) / 256 * 256;
+        return p;
+    };
+    w.D = nullptr;
+    w.Dt = (double *)take(8 * n2);
+    w.Dmax = (double *)take(8 * (size_t)S.nshell * S.nshell);
+    w.X = (double *)take(8 * n2);
+    w.Y = (double *)take(8 * n2);
+    w.Jt = (double *)take(8 * n2);
+    w.Kt = (double *)take(8 * n2);
+    w.Jo = (double *)take(8 * m2);
+    w.Ko = (double *)take(8 * m2);
+    w.scal = (double *)take(8 * 4);
+    w.dmaxg = (unsigned long long *)take(8);
+    w.cnt = (unsigned long long *)take(8 * kNumCounters);
+    w.wcnt = (unsigned long long *)take(8 * 42);
+    w.L = (double *)take(8 * n * (size_t)h->lr_rmax);
+    w.pw = (double *)take(8 * (n + 2 * nblk + 4));
+    w.pwi = (int *)take(4 * 2 * nblk);
+    w.ctl = (int *)take(4 * 4);
+    w.hd = (double *)take(8 * (size_t)std::max(1L, h->hd_base[kNumClass]));
+    if (off > cap) return fail(PBC_JK_ENOMEM, "the cell's work buffers exceed the static scratch array");
+    // F and T hold 2 gc matrices each (T at least one), rho 2 gc values
+    const size_t per_g = 2 * 8 * n2 * 2 + 2 * 8 + 3 * 256;
+    const size_t left = cap - off;
+    long gc = (long)std::min<size_t>((size_t)std::max(h->gchunk, 1), left / per_g);
+    if (gc < 1) return fail(PBC_JK_ENOMEM, "the cell's work buffers exceed the static scratch array");
+    w.F = (double *)take(8 * 2 * (size_t)gc * n2);
+    w.T = (double *)take(8 * std::max<size_t>(2 * (size_t)gc * n2, n2));
+    w.rho = (double *)take(8 * 2 * (size_t)gc);
+    if (off > cap) return fail(PBC_JK_ENOMEM, "the cell's work buffers exceed the static scratch array");
+    w.gchunk = (int)gc;
+    return 0;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *pbc_jk_last_error(void) { return g_err.c_str(); }
@@ -1030,6 +1129,29 @@ int pbc_jk_one_electron(pbc_jk *h, double *S_out, double *T_out, double *V_out, 
     }
     HIPCHK(hipStreamSynchronize(st));
     return 0;
+}
+
+int pbc_jk_build_device_static(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, double *E_K,
+                               void *stream)
+{
+    g_err.clear();
+    if (!h) return fail(PBC_JK_EINVAL, "handle is NULL");
+    if (!dD) return fail(PBC_JK_EINVAL, "D is NULL");
+    HIPCHK(hipSetDevice(h->device));
+    char *base = nullptr;
+    int rc = scratch_address(h->device, &base);
+    if (rc) return rc;
+    WorkBufs mine{};
+    if ((rc = carve_work(h, base, kScratchBytes, mine))) return rc;
+    // the kernels of this build take the scratch addresses; the handle's own
+    // buffers are put back once the launches are queued
+    const WorkBufs own = work_of(h);
+    set_work(h, mine);
+    auto t0 = std::chrono::steady_clock::now();
+    rc = run_build(h, dD, dJ, dK, E_J, E_K, (hipStream_t)stream);
+    h->st.t_build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    set_work(h, own);   // the counters of this build stay readable in the scratch array
+    return rc;
 }
 
 int pbc_jk_build(pbc_jk *h, const double *D, double *J, double *K, double *E_J, double *E_K)

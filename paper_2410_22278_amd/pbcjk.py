@@ -26,7 +26,7 @@ PART_SR, PART_LR, PART_SELF = 1, 2, 4
 LR_AUTO, LR_DENSE = 0, 1
 
 # every symbol the header declares
-EXPORTS = ["pbc_jk_create", "pbc_jk_build", "pbc_jk_build_device",
+EXPORTS = ["pbc_jk_create", "pbc_jk_build", "pbc_jk_build_device", "pbc_jk_build_device_static",
            "pbc_jk_one_electron", "pbc_jk_destroy",
            "pbc_jk_nbf", "pbc_jk_stats", "pbc_jk_set_parts", "pbc_jk_set_sr_classes", "pbc_jk_set_lr", "pbc_jk_last_error",
            "pbc_jk_server_create", "pbc_jk_server_submit", "pbc_jk_server_wait", "pbc_jk_server_cancel",
@@ -110,6 +110,8 @@ def load():
     lib.pbc_jk_build_device.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_double),
                                         POINTER(c_double), c_void_p]
     lib.pbc_jk_build_device.restype = c_int
+    lib.pbc_jk_build_device_static.argtypes = lib.pbc_jk_build_device.argtypes
+    lib.pbc_jk_build_device_static.restype = c_int
     lib.pbc_jk_one_electron.argtypes = [c_void_p, POINTER(c_double), POINTER(c_double), POINTER(c_double),
                                         POINTER(c_double)]
     lib.pbc_jk_one_electron.restype = c_int
@@ -260,6 +262,22 @@ def pbc_jk_build_device(h: int, dD, dJ=None, dK=None, energies: bool = True, str
     return (ej.value, ek.value if want_ek else None) if energies else None
 
 
+def pbc_jk_build_device_static(h: int, dD, dJ=None, dK=None, energies: bool = True, stream=None):
+    """pbc_jk_build_device with the work buffers in the library's static
+    device array (no device allocation); same arguments and results."""
+    lib = load()
+    _check_device_buffers(h, dD=dD, dJ=dJ, dK=dK)
+    ej, ek = c_double(), c_double()
+    want_ek = energies and dK is not None
+    rc = lib.pbc_jk_build_device_static(c_void_p(h), c_void_p(dD.data_ptr()),
+                                        c_void_p(dJ.data_ptr()) if dJ is not None else None,
+                                        c_void_p(dK.data_ptr()) if dK is not None else None,
+                                        byref(ej) if energies else None, byref(ek) if want_ek else None,
+                                        _stream_ptr(stream))
+    _check(rc)
+    return (ej.value, ek.value if want_ek else None) if energies else None
+
+
 def pbc_jk_one_electron(h: int, want_S=True, want_T=True, want_V=True, want_E_nuc=True):
     """Returns (S, T, V, E_nuc) of the handle's cell (None for what was not
     asked for)."""
@@ -317,6 +335,9 @@ class Handle:
 
     def build_device(self, dD, dJ=None, dK=None, energies=True, stream=None):
         return pbc_jk_build_device(self.h, dD, dJ, dK, energies, stream)
+
+    def build_device_static(self, dD, dJ=None, dK=None, energies=True, stream=None):
+        return pbc_jk_build_device_static(self.h, dD, dJ, dK, energies, stream)
 
     def stats(self):
         return pbc_jk_stats(self.h)
