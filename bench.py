@@ -5,7 +5,14 @@ One step = one full build (density prep, short-range J/K, reciprocal J/K,
 self term, back-transform, energies) through pbc_jk_build_device with the
 density already resident in HBM.  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--workload cfg2|cfg1]
+  python bench.py [--steps K] [--warmup W] [--workload headline|cfg1|cfg2|cfg3|cfg4|cfg4m|cfg5]
+
+The default (headline) times the 64-water cell in FP64 for exactly K builds
+after W warm-ups (the line's value), then in the same run the same cell in
+mixed precision (same K and W), a J-only build (the J-engine), and the
+512-atom diamond cell in FP64 and in mixed precision (one warm-up and one
+timed build each: at about a minute a build, K of them would not fit the
+run's time limit), each with its error against the stored oracle results.
 """
 import argparse
 import json
@@ -18,6 +25,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "Fock J+K builds/s & screened quartets/s, FP64 vs mixed; p50/p99 latency"
+T_START = time.perf_counter()
+BUDGET_S = 480.0    # the optional legs stop before this many seconds of the run
 FP64_MFMA_PEAK_TFLOPS = 78.6
 # FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP (FMA) x 2.4 GHz
 FP64_VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
@@ -101,6 +110,7 @@ def cpu_baseline(system, name):
 
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    model = cpu_info()
     if name == "cfg3":
         name = "cfg2"    # the oracle is FP64 only: same workload
     if name in ("cfg4", "cfg4m"):
@@ -109,7 +119,7 @@ def cpu_baseline(system, name):
         t0 = time.perf_counter()
         oracle.jk(system)
         t = time.perf_counter() - t0
-        return {"value": 1.0 / t, "unit": "builds/s", "cores": threads, "kind": "oracle",
+        return {"value": 1.0 / t, "unit": "builds/s", "cores": threads, "cpu": model, "kind": "oracle",
                 "sample": "one full cfg1 build"}
     shells = [0, 3, 7]    # O s, O p, H s of the first water
     pl = oracle.pair_list(system)
@@ -126,7 +136,7 @@ def cpu_baseline(system, name):
     oracle.jk(system, parts="self")
     t_self = time.perf_counter() - t0
     total = t_sr + t_lr + t_self
-    return {"value": 1.0 / total, "unit": "builds/s", "cores": threads, "kind": "oracle",
+    return {"value": 1.0 / total, "unit": "builds/s", "cores": threads, "cpu": model, "kind": "oracle",
             "sample": (f"short-range rows of shells {shells} ({100 * frac:.2f}% of the bra pairs) "
                        f"scaled by 1/fraction; reciprocal part over {ng_s} of {len(G)} G vectors scaled "
                        f"by {len(G)}/{ng_s}; self term in full; est. full build {total:.0f} s")}
@@ -186,15 +196,194 @@ def serve(args, np, torch, inputs, pbcjk):
     print(json.dumps(out), flush=True)
 
 
+
+
+def oracle_counts(name):
+    """Screened ordered primitive quartets and (quartet, R1) terms of the FP64
+    oracle's full build of the 64-water cell (stored with its J and K)."""
+    if name not in ("cfg2", "cfg3"):
+        return None
+    try:
+        import numpy as np
+        g = np.load(os.path.join(ROOT, "tests", "golden", "cfg2_full.npz"))
+        return {"ordered_quartets": float(g["n_quartets"]), "terms": float(g["n_terms"]),
+                "definition": "ordered primitive quartets kept by the density-weighted Schwarz screen and "
+                              "their (quartet, R1) terms, counted by the oracle (each unordered quartet twice)"}
+    except (OSError, KeyError):
+        return None
+
+
+def time_workload(system, steps, warmup, np, torch, pbcjk, want_K=True, tag="", parts=None):
+    """W untimed builds, then exactly `steps` timed builds through
+    pbc_jk_build_device with D resident in HBM.  Returns the timings, the
+    per-kernel accounting of the handle's counters, the last J, K (host) and
+    energies.  `parts`: a PART_* mask to build only those parts (profiling)."""
+    t_create = time.perf_counter()
+    h = pbcjk.Handle(system)
+    t_create = time.perf_counter() - t_create
+    if parts is not None:
+        h.set_parts(parts)
+    dD = torch.from_numpy(system.D).cuda()
+    dJ = torch.empty_like(dD)
+    dK = torch.empty_like(dD) if want_K else None
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        h.build_device(dD, dJ, dK, energies=True, stream=stream)
+    torch.cuda.synchronize()
+    print(f"{tag}: setup {t_create:.1f} s, warmup done ({warmup} builds)", file=sys.stderr, flush=True)
+    acc = {"lat": [], "gemm_ms": 0.0, "gemm_fl": 0.0, "n_gemm": 0, "y_ms": 0.0, "y_fl": 0.0, "n_y": 0,
+           "sfac_ms": 0.0, "sr_class_ms": [0.0] * 21, "sr_terms_class": [0.0] * 21,
+           "stage": {"sr": 0.0, "lr": 0.0, "other": 0.0}}
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    EJ = EK = None
+    st = None
+    for _ in range(steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        EJ, EK = h.build_device(dD, dJ, dK, energies=True, stream=stream)
+        e1.record(stream)
+        st = h.stats()
+        e1.synchronize()
+        acc["lat"].append(e0.elapsed_time(e1))
+        for k, f in (("gemm_ms", "t_gemm_ms"), ("gemm_fl", "gemm_flops"), ("n_gemm", "n_gemm"), ("y_ms", "t_y_ms"),
+                     ("y_fl", "y_flops"), ("n_y", "n_y"), ("sfac_ms", "t_sfac_ms")):
+            acc[k] += st[f]
+        for k, f in (("sr", "t_sr_ms"), ("lr", "t_lr_ms"), ("other", "t_other_ms")):
+            acc["stage"][k] += st[f]
+        for k in range(21):
+            acc["sr_class_ms"][k] += st["t_sr_class_ms"][k]
+            acc["sr_terms_class"][k] += st["terms_class"][k]
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    acc["ms_per_step"] = t_start.elapsed_time(t_end) / steps
+    acc["st"] = st
+    acc["E_J"], acc["E_K"] = EJ, EK
+    acc["J"] = dJ.cpu().numpy()
+    acc["K"] = dK.cpu().numpy() if want_K else None
+    acc["setup_s"] = t_create
+    h.close()
+    print(f"{tag}: timed {steps} builds: {acc['ms_per_step']:.2f} ms/build", file=sys.stderr, flush=True)
+    return acc
+
+
+def kernel_candidates(acc, steps):
+    """Per-kernel device time and algorithmic FLOPs per build: the exchange
+    GEMMs (FP64 MFMA) and each short-range class pair (FP64 VALU)."""
+    st = acc["st"]
+    gk = st["gemm_kernel"]
+    gemm_name = f"k_dgemm<{gk}>"
+    gemm_role = {0: "dense exchange T_G = F_G D, K += W_G T_G F_G, and the self term",
+                 3: "low-rank exchange accumulation K += sum_G Y_G Y_G^T on the upper tiles (D = L L^T, "
+                    "FLOPs counted on the upper triangle)"}[gk]
+    cands = [{"kernel": f"{gemm_name}: {gemm_role}", "name": gemm_name, "bound": "mfma",
+              "ms_per_build": acc["gemm_ms"] / steps, "flops_per_build": acc["gemm_fl"] / steps,
+              "launches_per_build": acc["n_gemm"] / steps, "peak": FP64_MFMA_PEAK_TFLOPS}]
+    if acc["y_ms"] > 0:
+        cands.append({"kernel": "k_dgemm<2>: low-rank exchange products Y_G^T = L^T F_G", "name": "k_dgemm<2>",
+                      "bound": "mfma", "ms_per_build": acc["y_ms"] / steps, "flops_per_build": acc["y_fl"] / steps,
+                      "launches_per_build": acc["n_y"] / steps, "peak": FP64_MFMA_PEAK_TFLOPS})
+    for k in range(21):
+        t = acc["sr_class_ms"][k] / steps
+        if t <= 0:
+            continue
+        cb, ck = SLOTS[k]
+        la, lb = CLASSES[cb]
+        lc, ld = CLASSES[ck]
+        if (st["sr_jengine_mask"] >> k) & 1:
+            name = f"k_sr_j<{la}, {lb}, {lc}, {ld}>"
+        elif (st["sr_kernel_mask"] >> k) & 1:
+            name = f"k_sr_coop<{la}, {lb}, {lc}, {ld}> (or k_sr_coop2)"
+        elif (cb, ck) in COOP_SLOTS:
+            name = f"k_sr_jk<{la}, {lb}, {lc}, {ld}, double, *> (component slices)"
+        else:
+            fold = "true" if (st["sr_fold_mask"] >> k) & 1 else "false"
+            name = f"k_sr_jk<{la}, {lb}, {lc}, {ld}, double, {fold}, 0, {_nc(lc)}>"
+        cands.append({"kernel": f"{name}: short-range, class pair ({CLASS_NAMES[cb]}|{CLASS_NAMES[ck]})",
+                      "name": name, "bound": "alu", "ms_per_build": t,
+                      "flops_per_build": acc["sr_terms_class"][k] / steps * sr_flops_per_term(cb, ck),
+                      "launches_per_build": 1.0, "peak": FP64_VALU_PEAK_TFLOPS})
+    cands.sort(key=lambda c: -c["ms_per_build"])
+    return cands
+
+
+def roof(c):
+    ach = c["flops_per_build"] / (c["ms_per_build"] * 1e-3) / 1e12 if c["ms_per_build"] > 0 else 0.0
+    return {"kernel": c["kernel"], "bound": c["bound"], "achieved": ach, "peak": c["peak"], "unit": "TFLOP/s",
+            "frac": ach / c["peak"], "traffic": traffic_for(c["name"]),
+            "launches_per_build": c["launches_per_build"],
+            "avg_launch_ms": c["ms_per_build"] / max(1e-9, c["launches_per_build"]),
+            "ms_per_build": c["ms_per_build"], "flops_per_build": c["flops_per_build"]}
+
+
+def sr_summary(acc, steps, cands):
+    ms = sum(acc["sr_class_ms"]) / steps
+    fl = sum(c["flops_per_build"] for c in cands if c["bound"] == "alu")
+    tf = fl / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+    return {"ms_per_build": ms, "achieved_tflops": tf, "frac_fp64_valu": tf / FP64_VALU_PEAK_TFLOPS}
+
+
+def errors_vs_golden(name, system, acc, np):
+    """Errors against the stored FP64 oracle results (tests/golden), when the
+    file for this workload exists: max|dJ|, max|dK| and dE_J, dE_K per atom
+    (full matrices), or max|dJ|, max|dK| on the stored rows."""
+    gdir = os.path.join(ROOT, "tests", "golden")
+    try:
+        if name in ("cfg2", "cfg3"):
+            g = np.load(os.path.join(gdir, "cfg2_full.npz"))
+            n = int(g["n"])
+            iu = np.triu_indices(n)
+            out = {"reference": "tests/golden/cfg2_full.npz (FP64 oracle, full build)",
+                   "max_abs_dJ": float(np.abs(acc["J"][iu] - g["J"]).max())}
+            if acc["K"] is not None:
+                out["max_abs_dK"] = float(np.abs(acc["K"][iu] - g["K"]).max())
+                out["dE_K_per_atom"] = float((acc["E_K"] - float(g["E_K"])) / system.natom)
+            out["dE_J_per_atom"] = float((acc["E_J"] - float(g["E_J"])) / system.natom)
+            return out
+        if name in ("cfg4", "cfg4m"):
+            g = np.load(os.path.join(gdir, "cfg4_rows.npz"))
+            rows = g["rows"]
+            J = g["J_sr"] + g["J_lrself"]
+            K = g["K_sr"] + g["K_lrself"]
+            return {"reference": "tests/golden/cfg4_rows.npz (FP64 oracle rows of 3 shells)",
+                    "rows": int(len(rows)), "max_abs_dJ": float(np.abs(acc["J"][rows] - J).max()),
+                    "max_abs_dK": float(np.abs(acc["K"][rows] - K).max())}
+    except (OSError, KeyError):
+        return None
+    return None
+
+
+def cpu_info():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="headline", choices=["headline"] + sorted(WORKLOADS),
+                    help="headline (default): cfg2 FP64 timed as the line's value, with the cfg3 mixed, "
+                         "cfg2 J-only and cfg4 FP64/mixed legs in the same line; or one workload alone")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--requests", type=int, default=32, help="cfg5: requests of the stream to run")
+    ap.add_argument("--no-cfg4", action="store_true", help="headline: leave out the cfg4 legs")
+    ap.add_argument("--requests", type=int, default=256, help="cfg5: requests of the stream to run")
     ap.add_argument("--rate-factor", type=float, default=0.8, help="cfg5: arrival rate / saturated rate")
+    ap.add_argument("--parts", default="all", choices=["all", "sr", "lr", "self", "lr+self"],
+                    help="build only these parts of J and K (profiling one stream alone); the line then "
+                         "reports that partial build and no legs")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized float64 buffer 3 times on the GPU (counter calibration)")
     args = ap.parse_args()
@@ -223,153 +412,113 @@ def main():
     if args.workload == "cfg5":
         serve(args, np, torch, inputs, pbcjk)
         return
-    system = inputs.CONFIGS[args.workload]()
-    h = pbcjk.Handle(system)
-    dD = torch.from_numpy(system.D).cuda()
-    dJ = torch.empty_like(dD)
-    dK = torch.empty_like(dD)
-    stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        h.build_device(dD, dJ, dK, energies=True, stream=stream)
-    torch.cuda.synchronize()
-    print(f"warmup done ({args.warmup} builds)", file=sys.stderr, flush=True)
-
-    lat, gemm_ms, gemm_fl, sfac_ms, n_gemm = [], 0.0, 0.0, 0.0, 0
-    y_ms, y_fl, n_y = 0.0, 0.0, 0
-    sr_class_ms, sr_terms_class = [0.0] * 21, [0.0] * 21
-    stage = {"sr": 0.0, "lr": 0.0, "other": 0.0}
-    quartets = terms = 0.0
-    torch.cuda.synchronize()
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
-    wall0 = time.perf_counter()
-    t_start.record(stream)
-    for k in range(args.steps):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        EJ, EK = h.build_device(dD, dJ, dK, energies=True, stream=stream)
-        e1.record(stream)
-        st = h.stats()
-        e1.synchronize()
-        lat.append(e0.elapsed_time(e1))
-        gemm_ms += st["t_gemm_ms"]
-        y_ms += st["t_y_ms"]
-        y_fl += st["y_flops"]
-        n_y += st["n_y"]
-        gemm_fl += st["gemm_flops"]
-        n_gemm += st["n_gemm"]
-        sfac_ms += st["t_sfac_ms"]
-        stage["sr"] += st["t_sr_ms"]
-        stage["lr"] += st["t_lr_ms"]
-        stage["other"] += st["t_other_ms"]
-        quartets, terms = st["quartets"], st["terms"]
-        for k in range(21):
-            sr_class_ms[k] += st["t_sr_class_ms"][k]
-            sr_terms_class[k] += st["terms_class"][k]
-    t_end.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    total_ms = t_start.elapsed_time(t_end)
-    ms_per_step = total_ms / args.steps
-    print(f"timed {args.steps} builds: {ms_per_step:.2f} ms/build (wall {wall:.2f} s)",
-          file=sys.stderr, flush=True)
-
-    lat = np.array(lat)
+    name = "cfg2" if args.workload == "headline" else args.workload
+    system = inputs.CONFIGS[name]()
+    parts = {"all": None, "sr": pbcjk.PART_SR, "lr": pbcjk.PART_LR, "self": pbcjk.PART_SELF,
+             "lr+self": pbcjk.PART_LR | pbcjk.PART_SELF}[args.parts]
+    acc = time_workload(system, args.steps, args.warmup, np, torch, pbcjk, tag=name, parts=parts)
     steps = args.steps
-    # GEMM instantiation that formed the reciprocal exchange
-    gk = st["gemm_kernel"]
-    gemm_name = f"k_dgemm<{gk}>"
-    gemm_role = {0: "dense exchange T_G = F_G D, K += W_G T_G F_G, and the self term",
-                 3: "low-rank exchange accumulation K += sum_G Y_G Y_G^T on the upper tiles (D = L L^T, "
-                    "FLOPs counted on the upper triangle)"}[gk]
-    cands = [{
-        "kernel": f"{gemm_name}: {gemm_role}", "name": gemm_name, "bound": "mfma",
-        "ms_per_build": gemm_ms / steps, "flops_per_build": gemm_fl / steps,
-        "launches_per_build": n_gemm / steps, "peak": FP64_MFMA_PEAK_TFLOPS,
-    }]
-    if y_ms > 0:
-        cands.append({
-            "kernel": "k_dgemm<2>: low-rank exchange products Y_G^T = L^T F_G", "name": "k_dgemm<2>",
-            "bound": "mfma", "ms_per_build": y_ms / steps, "flops_per_build": y_fl / steps,
-            "launches_per_build": n_y / steps, "peak": FP64_MFMA_PEAK_TFLOPS,
-        })
-    for k in range(21):
-        t = sr_class_ms[k] / steps
-        if t <= 0:
-            continue
-        cb, ck = SLOTS[k]
-        la, lb = CLASSES[cb]
-        lc, ld = CLASSES[ck]
-        fold = "true" if (st["sr_fold_mask"] >> k) & 1 else "false"
-        if (st["sr_kernel_mask"] >> k) & 1:
-            name = f"k_sr_coop<{la}, {lb}, {lc}, {ld}> (or k_sr_coop2)"
-        elif (cb, ck) in COOP_SLOTS:
-            name = f"k_sr_jk<{la}, {lb}, {lc}, {ld}, double, {fold}, *> (component slices)"
-        else:
-            name = f"k_sr_jk<{la}, {lb}, {lc}, {ld}, double, {fold}, 0, {_nc(lc)}>"
-        cands.append({
-            "kernel": f"{name}: short-range J/K, class pair ({CLASS_NAMES[cb]}|{CLASS_NAMES[ck]})", "name": name,
-            "bound": "alu", "ms_per_build": t, "flops_per_build": sr_terms_class[k] / steps * sr_flops_per_term(cb, ck),
-            "launches_per_build": 1.0, "peak": FP64_VALU_PEAK_TFLOPS,
-        })
-
-    def roof(c):
-        ach = c["flops_per_build"] / (c["ms_per_build"] * 1e-3) / 1e12 if c["ms_per_build"] > 0 else 0.0
-        return {"kernel": c["kernel"], "bound": c["bound"], "achieved": ach, "peak": c["peak"], "unit": "TFLOP/s",
-                "frac": ach / c["peak"], "traffic": traffic_for(c["name"]),
-                "launches_per_build": c["launches_per_build"],
-                "avg_launch_ms": c["ms_per_build"] / max(1e-9, c["launches_per_build"]),
-                "ms_per_build": c["ms_per_build"], "flops_per_build": c["flops_per_build"]}
-
-    cands.sort(key=lambda c: -c["ms_per_build"])
+    cands = kernel_candidates(acc, steps)
     roof_main = roof(cands[0])
     roof2 = roof(next((c for c in cands[1:] if c["bound"] != cands[0]["bound"]), cands[min(1, len(cands) - 1)]))
-    sr_total_ms = sum(sr_class_ms) / steps
-    sr_total_fl = sum(c["flops_per_build"] for c in cands if c["bound"] == "alu")
+    st = acc["st"]
+    lat = np.array(acc["lat"])
+    ms = acc["ms_per_step"]
     out = {
         "metric": METRIC,
-        "value": 1000.0 / ms_per_step,
+        "value": 1000.0 / ms,
         "unit": "builds/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": ms,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if system.thr.fp32_below == 0 else "f64+f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "nbf": system.nbf,
-                   "natom": system.natom,
+        "config": {"workload": f"{name}: {WORKLOADS[name]}", "nbf": system.nbf, "natom": system.natom,
                    "precision": "fp64" if system.thr.fp32_below == 0 else f"mixed (fp32 below {system.thr.fp32_below:g})"},
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),
-        "screened_quartets_per_s": quartets * 1000.0 / ms_per_step,
-        "screened_terms_per_s": terms * 1000.0 / ms_per_step,
-        "quartets_per_build": quartets,
-        "terms_per_build": terms,
+        "latency_samples": int(len(lat)),
+        "setup_s": acc["setup_s"],
+        "screened_quartets_per_s": st["quartets"] * 1000.0 / ms,
+        "screened_terms_per_s": st["terms"] * 1000.0 / ms,
+        "quartets_per_build": st["quartets"],
+        "terms_per_build": st["terms"],
         "terms_fp32_per_build": st["terms_fp32"],
         "group_pairs": st["n_group_pairs"],
-        "lr_exchange": {"form": "low-rank" if st["lr_rank"] >= 0 else "dense",
-                        "density_rank": st["lr_rank"], "factor_ms": st["t_chol_ms"]},
-        "stage_ms_per_build": {k: v / args.steps for k, v in stage.items()},
-        "E_J": EJ,
-        "E_K": EK,
+        "lr_exchange": {"form": "low-rank" if st["lr_rank"] >= 0 else "dense", "density_rank": st["lr_rank"],
+                        "factor_ms": st["t_chol_ms"]},
+        "stage_ms_per_build": {k: v / steps for k, v in acc["stage"].items()},
+        "E_J": acc["E_J"],
+        "E_K": acc["E_K"],
+        "vs_oracle": errors_vs_golden(name, system, acc, np),
         "roofline": roof_main,
         "roofline_secondary": roof2,
         "sr_classes": [{"class_pair": f"({CLASS_NAMES[SLOTS[k][0]]}|{CLASS_NAMES[SLOTS[k][1]]})",
-                        "ms_per_build": sr_class_ms[k] / steps, "terms_per_build": sr_terms_class[k] / steps}
-                       for k in range(21) if sr_class_ms[k] > 0],
-        "sr_all_classes": {"ms_per_build": sr_total_ms,
-                           "achieved_tflops": sr_total_fl / (sr_total_ms * 1e-3) / 1e12 if sr_total_ms > 0 else 0.0,
-                           "frac_fp64_valu": (sr_total_fl / (sr_total_ms * 1e-3) / 1e12 / FP64_VALU_PEAK_TFLOPS
-                                              if sr_total_ms > 0 else 0.0)},
+                        "ms_per_build": acc["sr_class_ms"][k] / steps, "terms_per_build": acc["sr_terms_class"][k] / steps}
+                       for k in range(21) if acc["sr_class_ms"][k] > 0],
+        "sr_all_classes": sr_summary(acc, steps, cands),
     }
-    h.close()
-    if not args.no_cpu_baseline:
+    if parts is not None:
+        out["parts"] = args.parts
+        out["vs_oracle"] = None
+        out["config"]["workload"] += f" (only the {args.parts} part)"
+    oc = oracle_counts(name)
+    if oc:
+        out["oracle_screened_terms_per_s"] = oc["terms"] * 1000.0 / ms
+        out["oracle_counts"] = oc
+    if args.workload == "headline" and parts is None:
+        del acc
+        legs = {}
+        # mixed precision on the same cell, same steps
+        s3 = inputs.cfg3()
+        a3 = time_workload(s3, steps, args.warmup, np, torch, pbcjk, tag="cfg3")
+        legs["mixed"] = {"workload": f"cfg3: {WORKLOADS['cfg3']}", "steps": steps, "warmup": args.warmup,
+                         "ms_per_step": a3["ms_per_step"], "builds_per_s": 1000.0 / a3["ms_per_step"],
+                         "speedup_vs_fp64": ms / a3["ms_per_step"],
+                         "terms_fp32_fraction": a3["st"]["terms_fp32"] / max(1.0, a3["st"]["terms"]),
+                         "stage_ms_per_build": {k: v / steps for k, v in a3["stage"].items()},
+                         "vs_oracle": errors_vs_golden("cfg3", s3, a3, np)}
+        del a3
+        # J alone (J-engine) on the same cell
+        nj = max(1, min(steps, 5))
+        aj = time_workload(system, nj, 1, np, torch, pbcjk, want_K=False, tag="cfg2 J-only")
+        legs["j_only"] = {"workload": "cfg2 without K (J-engine)", "steps": nj, "warmup": 1,
+                          "ms_per_step": aj["ms_per_step"], "fraction_of_jk_build": aj["ms_per_step"] / ms,
+                          "vs_oracle": errors_vs_golden("cfg2", system, aj, np)}
+        del aj
+        if not args.no_cfg4:
+            est = 200.0     # s: setup, one warm-up and one timed build of the diamond cell
+            for key, cname in (("cfg4_fp64", "cfg4"), ("cfg4_mixed", "cfg4m")):
+                if time.perf_counter() - T_START + est > BUDGET_S:
+                    legs[key] = {"workload": f"{cname}: {WORKLOADS[cname]}",
+                                 "skipped": f"would not finish within the run's {BUDGET_S:.0f} s budget"}
+                    continue
+                t_leg = time.perf_counter()
+                s4 = inputs.CONFIGS[cname]()
+                a4 = time_workload(s4, 1, 1, np, torch, pbcjk, tag=cname)
+                c4 = kernel_candidates(a4, 1)
+                legs[key] = {"workload": f"{cname}: {WORKLOADS[cname]}", "steps": 1, "warmup": 1,
+                             "ms_per_step": a4["ms_per_step"], "builds_per_s": 1000.0 / a4["ms_per_step"],
+                             "setup_s": a4["setup_s"],
+                             "stage_ms_per_build": a4["stage"], "terms_per_build": a4["st"]["terms"],
+                             "terms_fp32_fraction": a4["st"]["terms_fp32"] / max(1.0, a4["st"]["terms"]),
+                             "roofline": roof(c4[0]),
+                             "roofline_secondary": roof(next((c for c in c4[1:] if c["bound"] != c4[0]["bound"]),
+                                                            c4[min(1, len(c4) - 1)])),
+                             "sr_all_classes": sr_summary(a4, 1, c4),
+                             "vs_oracle": errors_vs_golden(cname, s4, a4, np)}
+                del a4
+                est = 1.1 * (time.perf_counter() - t_leg)
+            if "ms_per_step" in legs["cfg4_fp64"] and "ms_per_step" in legs["cfg4_mixed"]:
+                legs["cfg4_mixed"]["speedup_vs_fp64"] = legs["cfg4_fp64"]["ms_per_step"] / legs["cfg4_mixed"]["ms_per_step"]
+        out["legs"] = legs
+    if not args.no_cpu_baseline and parts is None:
         print("cpu baseline (oracle sample) ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(system, args.workload)
+        out["cpu_baseline"] = cpu_baseline(system, name)
     print(json.dumps(out), flush=True)
 
 

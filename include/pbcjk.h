@@ -234,6 +234,18 @@ int pbc_jk_nbf(const pbc_jk *h);
 /* Copies the handle's counters and timings into *out. */
 int pbc_jk_stats(const pbc_jk *h, pbc_jk_counters *out);
 
+/* Graph mode of the host-memory build (pbc_jk_build): when enabled, the
+ * first build captures its device work on the handle's stream (with the
+ * fork to and join from the handle's side streams) into a HIP graph, and
+ * later builds copy D in, replay the graph and copy J, K and the energies
+ * out.  The graph fixes the host-side choices of the captured build (kernel
+ * and lattice-sum order per class pair, the columns queued for the density
+ * factor); the factor's rank and the exchange form are still decided on the
+ * device at every replay.  Changing parts, class pairs or the exchange form,
+ * or disabling graph mode, drops the graph.  Device builds
+ * (pbc_jk_build_device, pbc_jk_build_device_static) are not affected. */
+int pbc_jk_set_graph(pbc_jk *h, int enable);
+
 /* Parts of the sum to evaluate (bit mask, default all): 1 = real-space
  * erfc sum, 2 = reciprocal sum, 4 = self term.  For per-part testing. */
 #define PBC_JK_PART_SR 1
@@ -293,6 +305,8 @@ typedef struct {
     int slots;            /* concurrent builds (worker threads / streams); 0 = 4            */
     int cache_cells;      /* keep idle cells resident for reuse (0/1)                       */
     double lr_budget_mb;  /* per-cell reciprocal-sum chunk budget; 0 = 1024 MB              */
+    int use_graphs;       /* with cache_cells: builds of a resident cell after its first one
+                             replay a captured HIP graph (pbc_jk_set_graph)                 */
 } pbc_jk_server_config;
 
 typedef struct {

@@ -98,6 +98,13 @@ struct pbc_jk {
     hipEvent_t ev_ctl = nullptr; // recorded after that copy
     int lr_cap = 0;              // columns queued for the last factor (upper bound of its rank)
     int y_tile = 64;             // output tile of the products Y_b^T = L^T F_b
+    // stream capture of the host-memory build: the device work of one build
+    // (D in d_D to J, K in d_Jo, d_Ko and the energies in d_scal) as a graph
+    bool use_graph = false, capturing = false;
+    // whether the last build's counters and factor decision were readable when
+    // the capture began (no event query runs inside a capture)
+    bool cnt_done = false, ctl_done = false;
+    hipGraphExec_t gexec = nullptr;
     double coop_ratio = kCoopRatio;
     int lr_rmax = 0;
     bool lr_ran = false;
@@ -211,8 +218,11 @@ void release_device(pbc_jk *h)
     h->timed = false;
 }
 
+void drop_graph(pbc_jk *h);
+
 void release(pbc_jk *h)
 {
+    drop_graph(h);
     release_device(h);
     for (auto &e : h->ev)
         if (e) (void)hipEventDestroy(e);
@@ -248,7 +258,7 @@ struct TimedLaunch {
     int slot = -1;
     TimedLaunch(pbc_jk *h_, hipStream_t st_, int kind, double flops) : h(h_), st(st_)
     {
-        if (h->profile && h->ntimed < pbc_jk::kMaxTimed) {
+        if (h->profile && !h->capturing && h->ntimed < pbc_jk::kMaxTimed) {
             slot = h->ntimed++;
             h->tkind[slot] = kind;
             h->tflops[slot] = flops;
@@ -464,6 +474,16 @@ int build_neighbours(pbc_jk *h)
     return 0;
 }
 
+// An event that has completed; a pending one leaves no error behind for the
+// launch checks that follow.
+bool event_done(hipEvent_t e)
+{
+    if (!e) return false;
+    const hipError_t q = hipEventQuery(e);
+    if (q != hipSuccess) (void)hipGetLastError();
+    return q == hipSuccess;
+}
+
 int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, double *E_K, hipStream_t st)
 {
     Setup &S = h->S;
@@ -474,7 +494,7 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
     double *Ko = dK ? dK : h->d_Ko;
     h->ntimed = 0;
     h->stat_cnt = h->d_cnt;
-    HIPCHK(hipEventRecord(h->ev[0], st));
+    if (!h->capturing) HIPCHK(hipEventRecord(h->ev[0], st));
 
     // B1: density in the scaled Cartesian basis, block maxima
     HIPCHK(launch_fill((double *)h->d_dmaxg, 1, 0.0, st));
@@ -488,7 +508,7 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
     HIPCHK(launch_fill((double *)h->d_cnt, kNumCounters, 0.0, st));
     // class pairs whose quartets had several shifts each in the last finished
     // build sum the shifts before the transforms
-    if (h->ev_cnt && hipEventQuery(h->ev_cnt) == hipSuccess)
+    if (h->capturing ? h->cnt_done : event_done(h->ev_cnt))
         for (int k = 0; k < 21; ++k) {
             const double nq = (double)h->h_cnt[24 + k], nt = (double)h->h_cnt[2 + k];
             if (nq > 0) {
@@ -585,13 +605,13 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
                 }
             }
     }
-    HIPCHK(hipEventRecord(h->ev[1], st));
+    if (!h->capturing) HIPCHK(hipEventRecord(h->ev[1], st));
 
     // B6 prelude (side stream, beside the short range): the density factor of
     // the low-rank exchange, whose rank stays on the device.
     const int nG = (int)S.Gw.size();
     const bool lr_on = (h->parts & PBC_JK_PART_LR) && nG > 0 && (wantJ || wantK);
-    HIPCHK(hipEventRecord(h->ev[4], ls));
+    if (!h->capturing) HIPCHK(hipEventRecord(h->ev[4], ls));
     SfacArgs sa{};
     sa.pairs = h->d_pairs; sa.sp_start = h->d_sp_start; sa.sp_pairs = h->d_sp_pairs;
     sa.sp_shA = h->d_sp_shA; sa.sp_shB = h->d_sp_shB; sa.sh_l = h->d_sh_l; sa.sh_aoc = h->d_sh_aoc;
@@ -629,7 +649,7 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
     // dense form runs instead (decided on the device); the next build then
     // queues the limit again.
     int cap = h->lr_rmax;
-    if (lowrank && h->ev_ctl && hipEventQuery(h->ev_ctl) == hipSuccess && h->h_ctl[2] && !h->h_ctl[1] &&
+    if (lowrank && (h->capturing ? h->ctl_done : event_done(h->ev_ctl)) && h->h_ctl[2] && !h->h_ctl[1] &&
         h->h_ctl[0] > 0)
         cap = std::min(h->lr_rmax, ((h->h_ctl[0] + 64 + 63) / 64) * 64);
     if (lowrank) {
@@ -654,7 +674,7 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
         HIPCHK(launch_lowrank_check(h->d_Dt, h->d_T, n, h->d_pw, h->d_ctl, ls));
         // a copy of the decision for the next build's column count and for the counters
         HIPCHK(hipMemcpyAsync(h->h_ctl, h->d_ctl, 4 * sizeof(int), hipMemcpyDeviceToHost, ls));
-        HIPCHK(hipEventRecord(h->ev_ctl, ls));
+        if (!h->capturing) HIPCHK(hipEventRecord(h->ev_ctl, ls));
     }
     h->lr_cap = cap;
 
@@ -759,10 +779,10 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
             }
         }
     }
-    HIPCHK(hipEventRecord(h->ev[5], ls));
+    if (!h->capturing) HIPCHK(hipEventRecord(h->ev[5], ls));
     HIPCHK(hipEventRecord(h->ev_join, ls));
     HIPCHK(hipStreamWaitEvent(st, h->ev_join, 0));
-    HIPCHK(hipEventRecord(h->ev[2], st));
+    if (!h->capturing) HIPCHK(hipEventRecord(h->ev[2], st));
 
     // B8: symmetrise, back-transform, energies
     if (wantJ) {
@@ -778,11 +798,11 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
         if (E_J) HIPCHK(launch_dot(dD, Jo, m2, h->d_scal + 1, st));
         if (E_K) HIPCHK(launch_dot(dD, Ko, m2, h->d_scal + 2, st));
     }
-    HIPCHK(hipEventRecord(h->ev[3], st));
+    if (!h->capturing) HIPCHK(hipEventRecord(h->ev[3], st));
     HIPCHK(hipMemcpyAsync(h->h_cnt, h->d_cnt, kNumCounters * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipEventRecord(h->ev_cnt, st));
-    h->timed = true;
-    if (E_J || E_K) {
+    if (!h->capturing) HIPCHK(hipEventRecord(h->ev_cnt, st));
+    h->timed = !h->capturing;
+    if ((E_J || E_K) && !h->capturing) {
         double e[2];
         HIPCHK(hipMemcpyAsync(e, h->d_scal + 1, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
@@ -800,6 +820,51 @@ int run_build(pbc_jk *h, const double *dD, double *dJ, double *dK, double *E_J, 
     if (rc && h->side) (void)hipStreamSynchronize(h->side);
     if (rc && h->side2) (void)hipStreamSynchronize(h->side2);
     return rc;
+}
+
+void drop_graph(pbc_jk *h)
+{
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+}
+
+// The device part of a host-memory build through a captured graph: the
+// first call captures one build (density in d_D; J, K into d_Jo, d_Ko; the
+// energies' dot products into d_scal) on the handle's stream, with the fork
+// to and join from its side streams, and later calls replay it.  Host-side
+// choices (fold and kernel per class pair, the columns queued for the
+// density factor) are those of the capture; everything the data decides
+// (the factor's rank, the exchange form) stays on the device.
+int run_graph(pbc_jk *h, hipStream_t st)
+{
+    if (!h->gexec) {
+        double dummy = 0.0;
+        h->cnt_done = event_done(h->ev_cnt);
+        h->ctl_done = event_done(h->ev_ctl);
+        h->capturing = true;
+        hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed);
+        if (e != hipSuccess) {
+            h->capturing = false;
+            return fail(PBC_JK_EDEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+        }
+        const int rc = run_build_streams(h, h->d_D, h->d_Jo, h->d_Ko, &dummy, &dummy, st);
+        hipGraph_t g = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(st, &g);
+        h->capturing = false;
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e2 != hipSuccess) return fail(PBC_JK_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e2));
+        const hipError_t e3 = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e3 != hipSuccess) {
+            h->gexec = nullptr;
+            return fail(PBC_JK_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e3));
+        }
+    }
+    HIPCHK(hipGraphLaunch(h->gexec, st));
+    return 0;
 }
 
 bool finite_all(const double *p, size_t n)
@@ -881,6 +946,7 @@ int handle_device(pbc_jk *h, Arena *arena, bool profile, double lr_budget_mb)
 void handle_drop_device(pbc_jk *h)
 {
     (void)hipSetDevice(h->device);
+    drop_graph(h);
     if (h->own) (void)hipStreamSynchronize(h->own);
     if (h->side) (void)hipStreamSynchronize(h->side);
     if (h->side2) (void)hipStreamSynchronize(h->side2);
@@ -1173,9 +1239,23 @@ int pbc_jk_build(pbc_jk *h, const double *D, double *J, double *K, double *E_J, 
     hipStream_t st = h->own;
     HIPCHK(hipMemcpyAsync(h->d_D, D, m2 * sizeof(double), hipMemcpyHostToDevice, st));
     double ej = 0, ek = 0;
-    int rc = run_build(h, h->d_D, J ? h->d_Jo : nullptr, K ? h->d_Ko : nullptr, E_J ? &ej : nullptr,
-                       E_K ? &ek : nullptr, st);
-    if (rc) return rc;
+    if (h->use_graph) {
+        const int rc = run_graph(h, st);
+        if (rc) {
+            if (h->side) (void)hipStreamSynchronize(h->side);
+            if (h->side2) (void)hipStreamSynchronize(h->side2);
+            return rc;
+        }
+        double e[2];
+        HIPCHK(hipMemcpyAsync(e, h->d_scal + 1, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        ej = 0.5 * e[0];
+        ek = -0.25 * e[1];
+    } else {
+        const int rc = run_build(h, h->d_D, J ? h->d_Jo : nullptr, K ? h->d_Ko : nullptr, E_J ? &ej : nullptr,
+                                 E_K ? &ek : nullptr, st);
+        if (rc) return rc;
+    }
     if (J) HIPCHK(hipMemcpyAsync(J, h->d_Jo, m2 * sizeof(double), hipMemcpyDeviceToHost, st));
     if (K) HIPCHK(hipMemcpyAsync(K, h->d_Ko, m2 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -1196,6 +1276,7 @@ int pbc_jk_nbf(const pbc_jk *h)
 int pbc_jk_set_lr(pbc_jk *h, int mode, double tol)
 {
     if (!h) return fail(PBC_JK_EINVAL, "handle is NULL");
+    drop_graph(h);
     if (mode != PBC_JK_LR_AUTO && mode != PBC_JK_LR_DENSE) return fail(PBC_JK_EINVAL, "unknown reciprocal exchange mode");
     if (!(tol < 1.0)) return fail(PBC_JK_EINVAL, "tolerance must be below 1");
     h->lr_mode = mode;
@@ -1206,14 +1287,28 @@ int pbc_jk_set_lr(pbc_jk *h, int mode, double tol)
 int pbc_jk_set_sr_classes(pbc_jk *h, int mask21)
 {
     if (!h) return fail(PBC_JK_EINVAL, "handle is NULL");
+    drop_graph(h);
     if (mask21 < 0 || mask21 >= (1 << 21)) return fail(PBC_JK_EINVAL, "class-pair mask has bits above 2^21");
     h->sr_classes = mask21;
+    return 0;
+}
+
+int pbc_jk_set_graph(pbc_jk *h, int enable)
+{
+    if (!h) return fail(PBC_JK_EINVAL, "handle is NULL");
+    HIPCHK(hipSetDevice(h->device));
+    if (!enable) {
+        if (h->own) HIPCHK(hipStreamSynchronize(h->own));
+        drop_graph(h);
+    }
+    h->use_graph = enable != 0;
     return 0;
 }
 
 int pbc_jk_set_parts(pbc_jk *h, int mask)
 {
     if (!h) return fail(PBC_JK_EINVAL, "handle is NULL");
+    drop_graph(h);
     if (mask & ~7) return fail(PBC_JK_EINVAL, "unknown part bits");
     h->parts = mask;
     return 0;

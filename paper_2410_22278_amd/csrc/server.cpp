@@ -378,6 +378,8 @@ void worker(pbc_jk_server *s)
         } else {
             r->cache_hit = 1;
             s->c.cache_hits++;
+            // repeated builds of a resident cell replay its captured graph
+            if (s->cfg.use_graphs) (void)pbc_jk_set_graph(cell->h, 1);
         }
 
         // build on the cell (busy, resident)

@@ -28,7 +28,7 @@ LR_AUTO, LR_DENSE = 0, 1
 # every symbol the header declares
 EXPORTS = ["pbc_jk_create", "pbc_jk_build", "pbc_jk_build_device", "pbc_jk_build_device_static",
            "pbc_jk_one_electron", "pbc_jk_destroy",
-           "pbc_jk_nbf", "pbc_jk_stats", "pbc_jk_set_parts", "pbc_jk_set_sr_classes", "pbc_jk_set_lr", "pbc_jk_last_error",
+           "pbc_jk_nbf", "pbc_jk_stats", "pbc_jk_set_graph", "pbc_jk_set_parts", "pbc_jk_set_sr_classes", "pbc_jk_set_lr", "pbc_jk_last_error",
            "pbc_jk_server_create", "pbc_jk_server_submit", "pbc_jk_server_wait", "pbc_jk_server_cancel",
            "pbc_jk_server_stats", "pbc_jk_server_destroy"]
 
@@ -68,7 +68,7 @@ class pbc_jk_counters(ctypes.Structure):
 
 class pbc_jk_server_config(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("slots", c_int), ("cache_cells", c_int),
-                ("lr_budget_mb", c_double)]
+                ("lr_budget_mb", c_double), ("use_graphs", c_int)]
 
 
 class pbc_jk_request_info(ctypes.Structure):
@@ -121,6 +121,8 @@ def load():
     lib.pbc_jk_nbf.restype = c_int
     lib.pbc_jk_stats.argtypes = [c_void_p, POINTER(pbc_jk_counters)]
     lib.pbc_jk_stats.restype = c_int
+    lib.pbc_jk_set_graph.argtypes = [c_void_p, c_int]
+    lib.pbc_jk_set_graph.restype = c_int
     lib.pbc_jk_set_parts.argtypes = [c_void_p, c_int]
     lib.pbc_jk_set_parts.restype = c_int
     lib.pbc_jk_set_sr_classes.argtypes = [c_void_p, c_int]
@@ -348,6 +350,9 @@ class Handle:
     def set_parts(self, mask):
         pbc_jk_set_parts(self.h, mask)
 
+    def set_graph(self, enable=True):
+        _check(load().pbc_jk_set_graph(c_void_p(self.h), 1 if enable else 0))
+
     def set_sr_classes(self, mask21):
         _check(load().pbc_jk_set_sr_classes(c_void_p(self.h), int(mask21)))
 
@@ -378,9 +383,10 @@ class Server:
     the ticket is waited for."""
 
     def __init__(self, hbm_budget: int = 0, slots: int = 4, cache_cells: bool = True,
-                 lr_budget_mb: float = 0.0):
+                 lr_budget_mb: float = 0.0, use_graphs: bool = False):
         lib = load()
-        cfg = pbc_jk_server_config(int(hbm_budget), int(slots), 1 if cache_cells else 0, float(lr_budget_mb))
+        cfg = pbc_jk_server_config(int(hbm_budget), int(slots), 1 if cache_cells else 0, float(lr_budget_mb),
+                                   1 if use_graphs else 0)
         s = c_void_p()
         _check(lib.pbc_jk_server_create(byref(cfg), byref(s)))
         self.s = s.value
