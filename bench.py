@@ -162,8 +162,15 @@ def serve(args, np, torch, inputs, pbcjk):
                     tickets[i] = srv.submit(r)
             th = threading.Thread(target=feeder)
             th.start()
+            res = []
+            for i in range(len(reqs)):
+                while tickets[i] is None:
+                    time.sleep(0.01)
+                res.append(srv.wait(tickets[i]))
+                if (i + 1) % 32 == 0:
+                    print(f"  {i + 1}/{len(reqs)} requests done, {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+                          flush=True)
             th.join()
-            res = [srv.wait(t) for t in tickets]
             wall = time.perf_counter() - t0
             st = srv.stats()
         bad = [r["error"] for r in res if r["status"] != 0]
@@ -348,9 +355,11 @@ def errors_vs_golden(name, system, acc, np):
             rows = g["rows"]
             J = g["J_sr"] + g["J_lrself"]
             K = g["K_sr"] + g["K_lrself"]
-            return {"reference": "tests/golden/cfg4_rows.npz (FP64 oracle rows of 3 shells)",
-                    "rows": int(len(rows)), "max_abs_dJ": float(np.abs(acc["J"][rows] - J).max()),
-                    "max_abs_dK": float(np.abs(acc["K"][rows] - K).max())}
+            out = {"reference": "tests/golden/cfg4_rows.npz (FP64 oracle rows of 3 shells)",
+                   "rows": int(len(rows)), "max_abs_dJ": float(np.abs(acc["J"][rows] - J).max())}
+            if acc["K"] is not None:
+                out["max_abs_dK"] = float(np.abs(acc["K"][rows] - K).max())
+            return out
     except (OSError, KeyError):
         return None
     return None
@@ -384,6 +393,8 @@ def main():
     ap.add_argument("--parts", default="all", choices=["all", "sr", "lr", "self", "lr+self"],
                     help="build only these parts of J and K (profiling one stream alone); the line then "
                          "reports that partial build and no legs")
+    ap.add_argument("--j-only", action="store_true",
+                    help="build J alone (the J-engine path; profiling); the line then reports that build")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized float64 buffer 3 times on the GPU (counter calibration)")
     args = ap.parse_args()
@@ -416,7 +427,8 @@ def main():
     system = inputs.CONFIGS[name]()
     parts = {"all": None, "sr": pbcjk.PART_SR, "lr": pbcjk.PART_LR, "self": pbcjk.PART_SELF,
              "lr+self": pbcjk.PART_LR | pbcjk.PART_SELF}[args.parts]
-    acc = time_workload(system, args.steps, args.warmup, np, torch, pbcjk, tag=name, parts=parts)
+    acc = time_workload(system, args.steps, args.warmup, np, torch, pbcjk, want_K=not args.j_only, tag=name,
+                        parts=parts)
     steps = args.steps
     cands = kernel_candidates(acc, steps)
     roof_main = roof(cands[0])
@@ -462,6 +474,9 @@ def main():
                        for k in range(21) if acc["sr_class_ms"][k] > 0],
         "sr_all_classes": sr_summary(acc, steps, cands),
     }
+    if args.j_only:
+        out["j_only"] = True
+        out["config"]["workload"] += " (J only)"
     if parts is not None:
         out["parts"] = args.parts
         out["vs_oracle"] = None
@@ -470,7 +485,7 @@ def main():
     if oc:
         out["oracle_screened_terms_per_s"] = oc["terms"] * 1000.0 / ms
         out["oracle_counts"] = oc
-    if args.workload == "headline" and parts is None:
+    if args.workload == "headline" and parts is None and not args.j_only:
         del acc
         legs = {}
         # mixed precision on the same cell, same steps
@@ -516,7 +531,7 @@ def main():
             if "ms_per_step" in legs["cfg4_fp64"] and "ms_per_step" in legs["cfg4_mixed"]:
                 legs["cfg4_mixed"]["speedup_vs_fp64"] = legs["cfg4_fp64"]["ms_per_step"] / legs["cfg4_mixed"]["ms_per_step"]
         out["legs"] = legs
-    if not args.no_cpu_baseline and parts is None:
+    if not args.no_cpu_baseline and parts is None and not args.j_only:
         print("cpu baseline (oracle sample) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(system, name)
     print(json.dumps(out), flush=True)

@@ -25,6 +25,12 @@ constexpr int kNumCounters = 48;     // see SRArgs::counters
 // Large d class pairs with component-slice launches of the per-lane kernel.
 bool sr_sliceable(int cb, int ck) { return !(cb == 5 && ck == 5); }
 
+// Builds without K: class pairs whose bra is an s-s pair keep the fused J/K
+// kernel, which is faster there than the J-engine (the Hermite densities of
+// the bra would be loaded per quartet for a one-term contraction); the others
+// run the J-engine.
+bool sr_jengine(int cb, int ck) { return cb >= 1 && ck >= cb; }
+
 // Class pairs (cb <= ck) with a per-lane register kernel: everything without
 // a d shell, and the d pairs (ds|ss), (dp|ss), (ds|ps), (dp|ps), (ds|pp), (ds|ds).
 bool sr_per_lane(int cb, int ck)
@@ -39,6 +45,8 @@ constexpr double kFoldRatio = 1.1;   // shifts per quartet above which the latti
 constexpr long kStage2Blocks = 4096; // workgroups aimed at by the split exchange accumulation
 constexpr double kCoopRatio = 4.5;   // shifts per quartet above which large d pairs use one
                                      // wavefront per group pair (it evaluates each shift once)
+constexpr int kFp32MinL = 4;         // mixed precision: class pairs of at least this total angular
+                                     // momentum run their low-bound group pairs in FP32
 
 thread_local std::string g_err;
 
@@ -106,6 +114,7 @@ struct pbc_jk {
     bool cnt_done = false, ctl_done = false;
     hipGraphExec_t gexec = nullptr;
     double coop_ratio = kCoopRatio;
+    int fp32_min_l = kFp32MinL;
     int lr_rmax = 0;
     bool lr_ran = false;
     size_t nbr_bytes_needed = 0;   // set once the neighbour lists are counted
@@ -114,6 +123,7 @@ struct pbc_jk {
     // at the same offsets, and their lengths (2 per class pair)
     int *d_w64b = nullptr, *d_w64k = nullptr, *d_w32b = nullptr, *d_w32k = nullptr;
     unsigned long long *d_wcnt = nullptr;
+    long long *d_pcc = nullptr;   // chunk counts of the order-preserving FP64/FP32 split
     unsigned long long *d_ncnt = nullptr;   // neighbour-list segment lengths (21)
     // counters of the last finished build (pinned copy, event-guarded), used
     // to choose per class pair whether the lattice sum is folded into R_{tuv}
@@ -208,8 +218,8 @@ void release_device(pbc_jk *h)
                    (void **)&h->d_Ko, (void **)&h->d_dmaxg, (void **)&h->d_cnt, (void **)&h->d_nbr_bra,
                    (void **)&h->d_nbr_ket, (void **)&h->d_L, (void **)&h->d_pw, (void **)&h->d_pwi,
                    (void **)&h->d_ctl, (void **)&h->d_w64b, (void **)&h->d_w64k, (void **)&h->d_w32b,
-                   (void **)&h->d_w32k, (void **)&h->d_wcnt, (void **)&h->d_ncnt, (void **)&h->d_hd,
-                   (void **)&h->d_xyz, (void **)&h->d_q};
+                   (void **)&h->d_w32k, (void **)&h->d_wcnt, (void **)&h->d_pcc, (void **)&h->d_ncnt,
+                   (void **)&h->d_hd, (void **)&h->d_xyz, (void **)&h->d_q};
     for (void **p : pp) {
         dfree(h, *p);
         *p = nullptr;
@@ -375,6 +385,7 @@ int create_device(pbc_jk *h)
     // reciprocal-space chunk: F and T hold 2 * gchunk matrices each
     if (const char *e = std::getenv("PBCJK_Y_TILE")) h->y_tile = std::atoi(e) == 128 ? 128 : 64;
     if (const char *e = std::getenv("PBCJK_COOP_RATIO")) h->coop_ratio = std::max(0.0, std::atof(e));
+    if (const char *e = std::getenv("PBCJK_FP32_MIN_L")) h->fp32_min_l = std::max(0, std::atoi(e));
     const int nG = (int)S.Gw.size();
     double budget_mb = h->lr_budget_mb > 0 ? h->lr_budget_mb : 16384.0;
     if (const char *e = std::getenv("PBCJK_LR_BUDGET_MB")) budget_mb = std::max(64.0, std::atof(e));
@@ -447,13 +458,19 @@ int build_neighbours(pbc_jk *h)
     h->nbr_off[21] = total;
     // the FP64/FP32 work lists exist only with mixed precision
     const size_t ne = (size_t)std::max(1L, total), nw = S.fp32_below > 0 ? ne : 1;
+    long max_chunks = 1;
+    for (int k = 0; k < 21; ++k)
+        max_chunks = std::max(max_chunks, (h->nbr_off[k + 1] - h->nbr_off[k] + kPartChunk - 1) / kPartChunk);
+    const size_t npcc = S.fp32_below > 0 ? 2 * (size_t)max_chunks : 2;
     h->nbr_bytes_needed = 2 * Arena::round_up(sizeof(int) * ne) + 4 * Arena::round_up(sizeof(int) * nw) +
                           Arena::round_up(42 * sizeof(unsigned long long)) +
-                          Arena::round_up(21 * sizeof(unsigned long long));
+                          Arena::round_up(21 * sizeof(unsigned long long)) +
+                          Arena::round_up(npcc * sizeof(long long));
     if ((rc = dalloc(h, &h->d_nbr_bra, ne)) || (rc = dalloc(h, &h->d_nbr_ket, ne)) ||
         (rc = dalloc(h, &h->d_w64b, nw)) || (rc = dalloc(h, &h->d_w64k, nw)) ||
         (rc = dalloc(h, &h->d_w32b, nw)) || (rc = dalloc(h, &h->d_w32k, nw)) ||
-        (rc = dalloc(h, &h->d_wcnt, 42)) || (rc = dalloc(h, &h->d_ncnt, 21)))
+        (rc = dalloc(h, &h->d_wcnt, 42)) || (rc = dalloc(h, &h->d_ncnt, 21)) ||
+        (rc = dalloc(h, &h->d_pcc, npcc)))
         return rc;
     slot = 0;
     for (int cb = 0; cb < kNumClass; ++cb)
@@ -553,13 +570,20 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
             for (int ck = cb; ck < kNumClass; ++ck, ++slot) {
                 const long e0 = h->nbr_off[slot], e1 = h->nbr_off[slot + 1];
                 if (e1 == e0 || !((h->sr_classes >> slot) & 1)) continue;
-                // d class pairs whose block does not fit in one lane's registers use
-                // one wavefront per group pair (FP64)
+                // d class pairs whose block does not fit in one lane's registers run
+                // the per-lane kernel one component slice at a time, or (tiny cells,
+                // and (dd|dd)) one wavefront per group pair (FP64)
                 const bool coop = !sr_per_lane(cb, ck);
+                const bool sliced = coop && !h->coop_d[slot] && sr_sliceable(cb, ck);
                 // mixed precision: the density screen splits the list into FP64
-                // and FP32 work lists; otherwise the kernels screen in place
-                const bool split = S.fp32_below > 0 && !coop;
+                // and FP32 work lists; otherwise the kernels screen in place.
+                // Below kFp32MinL the FP32 kernels save nothing: their quartets'
+                // cost is the FP64 screening, sphere and lattice search, and the
+                // second launch costs more than the FP32 arithmetic saves.
+                const bool split = S.fp32_below > 0 && (!coop || sliced) &&
+                                   kClassL[cb] + kClassL[ck] >= h->fp32_min_l;
                 PartArgs pa{};
+                pa.lat = a.lat;
                 pa.groups = h->d_groups; pa.gb0 = S.class_start[cb]; pa.gk0 = S.class_start[ck];
                 pa.bra = h->d_nbr_bra + e0; pa.ket = h->d_nbr_ket + e0; pa.n = e1 - e0;
                 pa.Dmax = h->d_Dmax; pa.nshell = S.nshell;
@@ -568,6 +592,7 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
                 pa.b64 = h->d_w64b + e0; pa.k64 = h->d_w64k + e0;
                 pa.b32 = h->d_w32b + e0; pa.k32 = h->d_w32k + e0;
                 pa.counts = h->d_wcnt + 2 * slot;
+                pa.chunk_counts = h->d_pcc;
                 if (split) HIPCHK(launch_partition(pa, st));
                 a.slot = slot;
                 a.gb0 = S.class_start[cb];
@@ -588,7 +613,7 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
                     if (h->fold[slot]) h->st.sr_fold_mask |= 1 << slot;
                     if (coop && (h->coop_d[slot] || !sr_sliceable(cb, ck))) h->st.sr_kernel_mask |= 1 << slot;
                     hipError_t e = hipErrorNotSupported;
-                    if (jonly) {
+                    if (jonly && sr_jengine(cb, ck)) {
                         e = launch_sr_j(cb, ck, a, st);
                         if (e == hipSuccess) {
                             h->st.sr_jengine_mask |= 1 << slot;
@@ -597,7 +622,7 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
                         if (e != hipErrorNotSupported) HIPCHK(e);
                     }
                     if (!coop) e = launch_sr_jk(cb, ck, a, prec == 1, h->fold[slot], st);
-                    else if (!h->coop_d[slot]) e = launch_sr_slices(cb, ck, a, h->fold[slot], st);
+                    else if (sliced) e = launch_sr_slices(cb, ck, a, prec == 1, h->fold[slot], st);
                     else e = hipErrorNotSupported;
                     if (e == hipErrorNotSupported && coop) e = launch_sr_coop(cb, ck, a, st);
                     if (e == hipErrorNotSupported) return fail(PBC_JK_ENOTSUP, "d-shell kernels not built");

@@ -16,30 +16,31 @@ __host__ __device__ constexpr int cy(int l, int k) { return l == 0 ? 0 : l == 1 
 __host__ __device__ constexpr int cz(int l, int k) { return l == 0 ? 0 : l == 1 ? (k == 2) : (k == 5 ? 2 : (k == 2 || k == 4) ? 1 : 0); }
 
 // One axis of Hermite coefficients with E^{00}_0 = 1 (the Gaussian factor
-// exp(-ab/p X_AB^2) is carried by the pair prefactor).
-template <int LA, int LB>
+// exp(-ab/p X_AB^2) is carried by the pair prefactor), in the value type T
+// (FP32 for the quartets of the single-precision work lists).
+template <int LA, int LB, typename T = double>
 struct EAxis {
-    double v[LA + 1][LB + 1][LA + LB + 1];
+    T v[LA + 1][LB + 1][LA + LB + 1];
 };
 
-template <int LA, int LB>
-__device__ __forceinline__ void herm_axis(double h, double xa, double xb, EAxis<LA, LB> &E)
+template <int LA, int LB, typename T = double>
+__device__ __forceinline__ void herm_axis(T h, T xa, T xb, EAxis<LA, LB, T> &E)
 {
 #pragma unroll
     for (int i = 0; i <= LA; ++i)
 #pragma unroll
         for (int j = 0; j <= LB; ++j)
 #pragma unroll
-            for (int t = 0; t <= LA + LB; ++t) E.v[i][j][t] = 0.0;
-    E.v[0][0][0] = 1.0;
+            for (int t = 0; t <= LA + LB; ++t) E.v[i][j][t] = T(0);
+    E.v[0][0][0] = T(1);
 #pragma unroll
     for (int i = 0; i < LA; ++i)
 #pragma unroll
         for (int t = 0; t <= i + 1; ++t) {
-            double r = 0.0;
+            T r = T(0);
             if (t >= 1) r += h * E.v[i][0][t - 1];
             if (t <= i) r += xa * E.v[i][0][t];
-            if (t + 1 <= i) r += (t + 1) * E.v[i][0][t + 1];
+            if (t + 1 <= i) r += T(t + 1) * E.v[i][0][t + 1];
             E.v[i + 1][0][t] = r;
         }
 #pragma unroll
@@ -48,10 +49,10 @@ __device__ __forceinline__ void herm_axis(double h, double xa, double xb, EAxis<
         for (int j = 0; j < LB; ++j)
 #pragma unroll
             for (int t = 0; t <= i + j + 1; ++t) {
-                double r = 0.0;
+                T r = T(0);
                 if (t >= 1) r += h * E.v[i][j][t - 1];
                 if (t <= i + j) r += xb * E.v[i][j][t];
-                if (t + 1 <= i + j) r += (t + 1) * E.v[i][j][t + 1];
+                if (t + 1 <= i + j) r += T(t + 1) * E.v[i][j][t + 1];
                 E.v[i][j + 1][t] = r;
             }
 }
@@ -221,27 +222,23 @@ __device__ __forceinline__ void boys_f32(double Td, const double *__restrict__ t
     }
 }
 
-// Short-range R^m_{000} in FP32 for a low-bound quartet.  Small arguments
-// (rho T < 1: both Boys arguments in the Taylor region, where the
-// difference 1 - c ... cancels) are evaluated in FP64 and rounded.
+// Short-range R^m_{000} in FP32 for the quartets of the FP32 work lists.
+// Their entries are chosen so that rho T >= 1 for every quartet and shift:
+// both Boys arguments are then outside the small-argument region, where the
+// difference of the two terms cancels (that region is evaluated in FP64, on
+// the FP64 lists).  The Boys arguments are formed in FP64.
 template <int L>
-__device__ __forceinline__ void sr_R0_mixed(double rho, double w2, double T, const double *__restrict__ tab,
-                                            const double *__restrict__ etab, float (&R0)[L + 1])
+__device__ __forceinline__ void sr_R0_f32(double rho, double w2, double T, const double *__restrict__ tab,
+                                          float (&R0)[L + 1])
 {
-    if (rho * T < 1.0) {
-        double R0d[L + 1];
-        sr_R0<L, kBoysTerms, true>(rho, w2, T, tab, etab, R0d);
-#pragma unroll
-        for (int m = 0; m <= L; ++m) R0[m] = (float)R0d[m];
-        return;
-    }
-    const double den = 1.0 / (rho + w2);
-    const double ap = rho * w2 * den;
+    const float rf = (float)rho, w2f = (float)w2;
+    const float s = __builtin_amdgcn_rsqf(rf + w2f);
+    const float apf = rf * w2f * (s * s);
     float F1[L + 1], F2[L + 1];
     boys_f32<L>(rho * T, tab, F1);
-    boys_f32<L>(ap * T, tab, F2);
-    float f1 = 1.0f, f2 = (float)sqrt(w2 * den);
-    const float r2 = (float)(-2.0 * rho), a2 = (float)(-2.0 * ap);
+    boys_f32<L>((double)apf * T, tab, F2);
+    float f1 = 1.0f, f2 = __builtin_amdgcn_sqrtf(w2f) * s;
+    const float r2 = -2.0f * rf, a2 = -2.0f * apf;
 #pragma unroll
     for (int m = 0; m <= L; ++m) {
         R0[m] = f1 * F1[m] - f2 * F2[m];
@@ -271,49 +268,99 @@ __device__ __forceinline__ bool quartet_sphere(const PairRec &b, const PairRec &
     return true;
 }
 
-__device__ __forceinline__ void lat_image(const LatArgs &lat, const double cen[3], int n0, int n1, int n2,
+__device__ __forceinline__ void lat_image(const LatArgs &lat, const double cen[3], double n0, double n1, double n2,
                                           double L[3])
 {
 #pragma unroll
     for (int x = 0; x < 3; ++x) L[x] = cen[x] - (n0 * lat.M[x] + n1 * lat.M[3 + x] + n2 * lat.M[6 + x]);
 }
 
-// Calls f(L) for every lattice translate L = cen - R1 with |L|^2 < rad2 (and
-// |L|^2 <= rcap2 when rcap2 > 0).  Fast path: when sqrt(rad2) <= Rmin - |L0|
-// for the rounded image L0, no other translate can lie inside the sphere.
-template <class F>
-__device__ __forceinline__ void for_images(const LatArgs &lat, const double cen[3], double rad2, double rcap2,
-                                           F &&f)
+// The nearest lattice translate of cen (its rounded fractional coordinates).
+__device__ __forceinline__ void nearest_translate(const LatArgs &lat, const double cen[3], double n[3])
 {
-    if (!(rad2 > 0.0)) return;   // empty sphere (also keeps the box below finite)
+#pragma unroll
+    for (int x = 0; x < 3; ++x)
+        n[x] = rint(cen[0] * lat.Minv[x] + cen[1] * lat.Minv[3 + x] + cen[2] * lat.Minv[6 + x]);
+}
+
+// Calls f(L, |L|^2) for every translate L = cen - R1 in the box of lattice
+// points that covers the sphere |L|^2 < rad2 (and |L|^2 <= rcap2 when
+// rcap2 > 0), testing each.  A translate n inside the sphere has
+// |f_x - n_x| = |sum_j L_j Minv[j][x]| <= |L| span_x < rad span_x for the
+// fractional coordinates f of cen, so the box holds the integers strictly
+// within rad span_x of f_x (rad slightly raised against rounding).
+template <class F>
+__device__ __forceinline__ void for_images_box(const LatArgs &lat, const double cen[3], double rad2, double rcap2,
+                                               F &&f)
+{
     double fr[3];
 #pragma unroll
     for (int x = 0; x < 3; ++x) fr[x] = cen[0] * lat.Minv[x] + cen[1] * lat.Minv[3 + x] + cen[2] * lat.Minv[6 + x];
-    double L[3];
-    lat_image(lat, cen, (int)rint(fr[0]), (int)rint(fr[1]), (int)rint(fr[2]), L);
-    const double L2 = L[0] * L[0] + L[1] * L[1] + L[2] * L[2];
     const double rad = rad2 * fast_rsqrt(rad2);
-    const double gap = lat.Rmin - rad;
-    // |L0| <= Rmin - rad: no other translate can lie inside the sphere
-    if (gap >= 0.0 && L2 <= gap * gap) {
-        if (L2 < rad2 && !(rcap2 > 0 && L2 > rcap2)) f(L, L2);
-        return;
-    }
     const double r = rad * (1.0 + 1e-9) + 1e-9;
     int lo[3], hi[3];
 #pragma unroll
     for (int x = 0; x < 3; ++x) {
-        lo[x] = (int)floor(fr[x] - r * lat.span[x]);
-        hi[x] = (int)ceil(fr[x] + r * lat.span[x]);
+        lo[x] = (int)ceil(fr[x] - r * lat.span[x]);
+        hi[x] = (int)floor(fr[x] + r * lat.span[x]);
     }
     for (int n0 = lo[0]; n0 <= hi[0]; ++n0)
         for (int n1 = lo[1]; n1 <= hi[1]; ++n1)
             for (int n2 = lo[2]; n2 <= hi[2]; ++n2) {
                 double Lb[3];
-                lat_image(lat, cen, n0, n1, n2, Lb);
+                lat_image(lat, cen, (double)n0, (double)n1, (double)n2, Lb);
                 const double Lb2 = Lb[0] * Lb[0] + Lb[1] * Lb[1] + Lb[2] * Lb[2];
                 if (Lb2 < rad2 && !(rcap2 > 0 && Lb2 > rcap2)) f(Lb, Lb2);
             }
+}
+
+// A radius at least sqrt(rad2): the FP32 square root (within a few units of
+// 2^-24 of it, rad2 rounded to FP32 included) raised by a relative 1e-6.
+__device__ __forceinline__ double radius_above(double rad2)
+{
+    return (double)(__builtin_amdgcn_sqrtf((float)rad2) * 1.000001f);
+}
+
+// Calls f(L, |L|^2) for every lattice translate L = cen - R1 with
+// |L|^2 < rad2 (and |L|^2 <= rcap2 when rcap2 > 0).  Fast path: when
+// |L0| <= Rmin - sqrt(rad2) for the rounded image L0, no other translate can
+// lie inside the sphere.
+template <class F>
+__device__ __forceinline__ void for_images(const LatArgs &lat, const double cen[3], double rad2, double rcap2,
+                                           F &&f)
+{
+    if (!(rad2 > 0.0)) return;   // empty sphere (also keeps the box below finite)
+    double n[3], L[3];
+    nearest_translate(lat, cen, n);
+    lat_image(lat, cen, n[0], n[1], n[2], L);
+    const double L2 = L[0] * L[0] + L[1] * L[1] + L[2] * L[2];
+    const double gap = lat.Rmin - radius_above(rad2);
+    if (gap >= 0.0 && L2 <= gap * gap) {
+        if (L2 < rad2 && !(rcap2 > 0 && L2 > rcap2)) f(L, L2);
+        return;
+    }
+    for_images_box(lat, cen, rad2, rcap2, f);
+}
+
+// As for_images, starting from the translate by the lattice vector S (an
+// integer combination of the lattice vectors) instead of the rounded image:
+// the caller passes the nearest translate of a nearby point (the group
+// centres of a work-list entry), which is that of most of its quartets, so
+// the fast path skips the rounding.  |cen - S| <= Rmin - sqrt(rad2) again
+// leaves no other translate inside the sphere, whatever S is.
+template <class F>
+__device__ __forceinline__ void for_images_from(const LatArgs &lat, const double cen[3], const double S[3],
+                                                double rad2, double rcap2, F &&f)
+{
+    if (!(rad2 > 0.0)) return;
+    double L[3] = {cen[0] - S[0], cen[1] - S[1], cen[2] - S[2]};
+    const double L2 = L[0] * L[0] + L[1] * L[1] + L[2] * L[2];
+    const double gap = lat.Rmin - radius_above(rad2);
+    if (gap >= 0.0 && L2 <= gap * gap) {
+        if (L2 < rad2 && !(rcap2 > 0 && L2 > rcap2)) f(L, L2);
+        return;
+    }
+    for_images_box(lat, cen, rad2, rcap2, f);
 }
 
 }  // namespace pbcjk

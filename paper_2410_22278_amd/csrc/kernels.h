@@ -74,6 +74,7 @@ hipError_t launch_nbr(const NbrArgs &a, hipStream_t st);
 // same bound is below fp32_below.  counts[0], counts[1]: list lengths (must
 // be zero on entry).
 struct PartArgs {
+    LatArgs lat;
     const GroupRec *groups;
     int gb0, gk0;
     const int *bra, *ket;
@@ -83,14 +84,16 @@ struct PartArgs {
     double d_schwarz, fp32_below;
     int split;
     int *b64, *k64, *b32, *k32;
-    unsigned long long *counts;
+    unsigned long long *counts;   // out: entries of the FP64 and of the FP32 list
+    long long *chunk_counts;      // work: 2 per chunk of kPartChunk entries
 };
+constexpr int kPartChunk = 4096;  // entries per counted chunk of the order-preserving split
 hipError_t launch_partition(const PartArgs &a, hipStream_t st);
 
 hipError_t launch_sr_jk(int cb, int ck, const SRArgs &a, bool f32, bool fold, hipStream_t st);
 // large d class pairs in the per-lane kernel, one launch per component slice
-hipError_t launch_sr_slices(int cb, int ck, const SRArgs &a, bool fold, hipStream_t st);
-hipError_t launch_sr_slices_dp(int cb, int ck, const SRArgs &a, bool fold, hipStream_t st);
+hipError_t launch_sr_slices(int cb, int ck, const SRArgs &a, bool f32, bool fold, hipStream_t st);
+hipError_t launch_sr_slices_dp(int cb, int ck, const SRArgs &a, bool f32, bool fold, hipStream_t st);
 // class pairs with total angular momentum >= 5 (one wavefront per group pair)
 hipError_t launch_sr_coop(int cb, int ck, const SRArgs &a, hipStream_t st);
 

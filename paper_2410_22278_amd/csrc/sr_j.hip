@@ -97,6 +97,9 @@ void k_sr_j(SRArgs a)
     constexpr int NHB = nherm_j(LAB), NHK = nherm_j(LCD);
     __shared__ double tab[kBoysNT * kBoysTerms];
     __shared__ double etab[kBoysNT];
+    // blocks past the work list's device-side length leave before staging
+    // the Boys table
+    if ((long)blockIdx.x * blockDim.x >= (long)*a.count) return;
     constexpr double kInvFact[kBoysTerms] = {1.0, 1.0, 1.0 / 2, 1.0 / 6, 1.0 / 24, 1.0 / 120, 1.0 / 720,
                                              1.0 / 5040, 1.0 / 40320};
     for (int i = threadIdx.x; i < kBoysNT * kBoysTerms; i += blockDim.x) {
@@ -130,6 +133,16 @@ void k_sr_j(SRArgs a)
 #pragma unroll
             for (int jj = 0; jj < ND; ++jj) acc_cd[i][jj] = 0.0;
         unsigned long long ent_terms = 0;
+        // the nearest lattice translate of the group centres' difference
+        // starts each quartet's image search
+        double S[3];
+        {
+            const double cg[3] = {gb.C[0] - gk.C[0], gb.C[1] - gk.C[1], gb.C[2] - gk.C[2]};
+            double n[3];
+            nearest_translate(a.lat, cg, n);
+#pragma unroll
+            for (int x = 0; x < 3; ++x) S[x] = n[0] * a.lat.M[x] + n[1] * a.lat.M[3 + x] + n[2] * a.lat.M[6 + x];
+        }
         // ket pairs outer, bra pairs inner, as in the J/K kernel (wave-uniform
         // bra records and Hermite densities read through the scalar unit)
         auto run = [&](auto bpairs, auto bhd, int pbs, int pbe) {
@@ -160,7 +173,7 @@ void k_sr_j(SRArgs a)
 #pragma unroll
                             for (int v = 0; v <= L - t - u; ++v) Rs[t][u][v] = 0.0;
                     int nimg = 0;
-                    for_images(a.lat, cen, rad2, a.rcap2, [&](const double *Lv, double L2) {
+                    for_images_from(a.lat, cen, S, rad2, a.rcap2, [&](const double *Lv, double L2) {
                         ++nimg;
                         double R0[L + 1];
                         sr_R0<L, kBoysTerms, true>(rho, a.w2, L2, tab, etab, R0);

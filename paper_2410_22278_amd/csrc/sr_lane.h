@@ -34,9 +34,10 @@ __device__ __forceinline__ PairRec load_pair(CPairPtr p)
 
 // acc += pref * sum_t E^ab_t sum_s (-1)^|s| E^cd_s R_{t+s}  (ket transform
 // first, then the bra), evaluated in the value type V.
-template <int LA, int LB, int LC, int LD, typename V, int IC0, int NIC>
-__device__ __forceinline__ void add_term(const EAxis<LA, LB> &Ex, const EAxis<LA, LB> &Ey, const EAxis<LA, LB> &Ez,
-                                         const EAxis<LC, LD> &Fx, const EAxis<LC, LD> &Fy, const EAxis<LC, LD> &Fz,
+template <int LA, int LB, int LC, int LD, typename V, int IC0, int NIC, typename EV>
+__device__ __forceinline__ void add_term(const EAxis<LA, LB, EV> &Ex, const EAxis<LA, LB, EV> &Ey,
+                                         const EAxis<LA, LB, EV> &Ez, const EAxis<LC, LD, EV> &Fx,
+                                         const EAxis<LC, LD, EV> &Fy, const EAxis<LC, LD, EV> &Fz,
                                          const V (&R)[LA + LB + LC + LD + 1][LA + LB + LC + LD + 1][LA + LB + LC + LD + 1],
                                          double pref, double (&acc)[ncart(LA)][ncart(LB)][NIC][ncart(LD)])
 {
@@ -167,6 +168,127 @@ __device__ __forceinline__ void scatter_block(const SRArgs &a, const double (&ac
         }
 }
 
+// One ket primitive pair Pk against the bra pairs [pbs, pbe) of a group,
+// which are stored by descending Q, so the first one that fails the
+// Cauchy-Schwarz test ends the sweep.  Per quartet: the density-weighted
+// screen, the real-space sphere, the lattice shifts inside it (searched from
+// the lattice translate S of the entry's group centres), and the block
+// accumulation into acc (see k_sr_jk).
+template <int LA, int LB, int LC, int LD, typename V, bool FOLD, int IC0, int NIC, class BP>
+__device__ __forceinline__ void bra_sweep(const SRArgs &a, BP bpairs, int pbs, int pbe, const PairRec &Pk, double wD,
+                                          const double (&S)[3], const double *tab, const double *etab,
+                                          double (&acc)[ncart(LA)][ncart(LB)][NIC][ncart(LD)],
+                                          unsigned long long &cnt_q, unsigned long long &cnt_t,
+                                          unsigned long long &ent_terms)
+{
+    constexpr int L = LA + LB + LC + LD;
+    constexpr bool F32 = sizeof(V) == 4;
+    // E coefficients in the list's precision (FP32 ones take half the registers)
+    typedef V EV;
+    EAxis<LC, LD, EV> Fx, Fy, Fz;
+    const EV hk = EV(0.5 * Pk.pad[0]);
+    herm_axis<LC, LD, EV>(hk, EV(Pk.PA[0]), EV(Pk.PB[0]), Fx);
+    herm_axis<LC, LD, EV>(hk, EV(Pk.PA[1]), EV(Pk.PB[1]), Fy);
+    herm_axis<LC, LD, EV>(hk, EV(Pk.PA[2]), EV(Pk.PB[2]), Fz);
+    for (int pb = pbs; pb < pbe; ++pb) {
+        const PairRec Pb = load_pair(bpairs + pb);
+        if (!(Pb.Q * Pk.Q * wD > a.d_schwarz)) break;
+        ++cnt_q;
+        double rad2;
+        if (!quartet_sphere(Pb, Pk, a.w2, a.d_ewald_R, rad2)) continue;
+        const double p = Pb.p, q = Pk.p;
+        const double rho = fast_rcp(Pb.pad[0] + Pk.pad[0]);
+        const double pref = Pb.cpre * Pk.cpre * kTwoPi52 * Pb.pad[0] * Pk.pad[0] * fast_rsqrt(p + q);
+        EAxis<LA, LB, EV> Ex, Ey, Ez;
+        const EV hb = EV(0.5 * Pb.pad[0]);
+        herm_axis<LA, LB, EV>(hb, EV(Pb.PA[0]), EV(Pb.PB[0]), Ex);
+        herm_axis<LA, LB, EV>(hb, EV(Pb.PA[1]), EV(Pb.PB[1]), Ey);
+        herm_axis<LA, LB, EV>(hb, EV(Pb.PA[2]), EV(Pb.PB[2]), Ez);
+        const double cen[3] = {Pb.P[0] - Pk.P[0], Pb.P[1] - Pk.P[1], Pb.P[2] - Pk.P[2]};
+        if (FOLD) {
+            // lattice sum of the Hermite integrals in FP64, one transform
+            double Rs[L + 1][L + 1][L + 1];
+#pragma unroll
+            for (int t = 0; t <= L; ++t)
+#pragma unroll
+                for (int u = 0; u <= L - t; ++u)
+#pragma unroll
+                    for (int v = 0; v <= L - t - u; ++v) Rs[t][u][v] = 0.0;
+            int nimg = 0;
+            for_images_from(a.lat, cen, S, rad2, a.rcap2, [&](const double *Lv, double L2) {
+                ++nimg;
+                if (F32) {
+                    float R0[L + 1];
+                    sr_R0_f32<L>(rho, a.w2, L2, tab, R0);
+                    float R[L + 1][L + 1][L + 1];
+                    herm_R<L, float>(R0, (float)Lv[0], (float)Lv[1], (float)Lv[2], R);
+#pragma unroll
+                    for (int t = 0; t <= L; ++t)
+#pragma unroll
+                        for (int u = 0; u <= L - t; ++u)
+#pragma unroll
+                            for (int v = 0; v <= L - t - u; ++v) Rs[t][u][v] += (double)R[t][u][v];
+                } else {
+                    double R0[L + 1];
+                    sr_R0<L, kBoysTerms, true>(rho, a.w2, L2, tab, etab, R0);
+                    double R[L + 1][L + 1][L + 1];
+                    herm_R<L, double>(R0, Lv[0], Lv[1], Lv[2], R);
+#pragma unroll
+                    for (int t = 0; t <= L; ++t)
+#pragma unroll
+                        for (int u = 0; u <= L - t; ++u)
+#pragma unroll
+                            for (int v = 0; v <= L - t - u; ++v) Rs[t][u][v] += R[t][u][v];
+                }
+            });
+            if (nimg == 0) continue;
+            cnt_t += nimg;
+            ent_terms += nimg;
+            V Rv[L + 1][L + 1][L + 1];
+#pragma unroll
+            for (int t = 0; t <= L; ++t)
+#pragma unroll
+                for (int u = 0; u <= L - t; ++u)
+#pragma unroll
+                    for (int v = 0; v <= L - t - u; ++v) Rv[t][u][v] = (V)Rs[t][u][v];
+            add_term<LA, LB, LC, LD, V, IC0, NIC, EV>(Ex, Ey, Ez, Fx, Fy, Fz, Rv, pref, acc);
+        } else {
+            for_images_from(a.lat, cen, S, rad2, a.rcap2, [&](const double *Lv, double L2) {
+                ++cnt_t;
+                ++ent_terms;
+                if (F32) {
+                    float R0[L + 1];
+                    sr_R0_f32<L>(rho, a.w2, L2, tab, R0);
+                    float R[L + 1][L + 1][L + 1];
+                    herm_R<L, float>(R0, (float)Lv[0], (float)Lv[1], (float)Lv[2], R);
+                    add_term<LA, LB, LC, LD, float, IC0, NIC, EV>(Ex, Ey, Ez, Fx, Fy, Fz, R, pref, acc);
+                } else {
+                    double R0[L + 1];
+                    sr_R0<L, kBoysTerms, true>(rho, a.w2, L2, tab, etab, R0);
+                    double R[L + 1][L + 1][L + 1];
+                    herm_R<L, double>(R0, Lv[0], Lv[1], Lv[2], R);
+                    add_term<LA, LB, LC, LD, double, IC0, NIC, EV>(Ex, Ey, Ez, Fx, Fy, Fz, R, pref, acc);
+                }
+            });
+        }
+    }
+}
+
+// Boys table rows L .. L + kBoysTerms - 1 into LDS, pre-divided by j! so
+// that the Taylor sum needs one FMA a term.
+template <int L>
+__device__ __forceinline__ void load_boys_table(const SRArgs &a, double *tab, double *etab)
+{
+    constexpr double kInvFact[kBoysTerms] = {1.0, 1.0, 1.0 / 2, 1.0 / 6, 1.0 / 24, 1.0 / 120, 1.0 / 720,
+                                             1.0 / 5040, 1.0 / 40320};
+    for (int i = threadIdx.x; i < kBoysNT * kBoysTerms; i += blockDim.x) {
+        int k = i / kBoysTerms, j = i - k * kBoysTerms;
+        tab[i] = a.boys[k * kBoysM + L + j] * kInvFact[j];
+    }
+    for (int i = threadIdx.x; i < kBoysNT; i += blockDim.x) etab[i] = a.bexp[i];
+    __syncthreads();
+}
+
 // IC0, NIC: the slice of the first ket shell's Cartesian components whose
 // block entries this launch accumulates (the whole shell by default; large d
 // class pairs run one launch per slice so that the slice fits in registers,
@@ -191,17 +313,12 @@ void k_sr_jk(SRArgs a)
     constexpr int NA = ncart(LA), NB = ncart(LB), ND = ncart(LD);
     constexpr bool COUNT = IC0 == 0;
     constexpr bool F32 = sizeof(V) == 4;
+    // blocks past the work list's device-side length (the grid is sized by
+    // the host-side upper bound) leave before staging the Boys table
+    if ((long)blockIdx.x * blockDim.x >= (long)*a.count) return;
     __shared__ double tab[kBoysNT * kBoysTerms];
     __shared__ double etab[kBoysNT];
-    // Taylor coefficients F_{L+j}(T_k) / j!
-    constexpr double kInvFact[kBoysTerms] = {1.0, 1.0, 1.0 / 2, 1.0 / 6, 1.0 / 24, 1.0 / 120, 1.0 / 720,
-                                             1.0 / 5040, 1.0 / 40320};
-    for (int i = threadIdx.x; i < kBoysNT * kBoysTerms; i += blockDim.x) {
-        int k = i / kBoysTerms, j = i - k * kBoysTerms;
-        tab[i] = a.boys[k * kBoysM + L + j] * kInvFact[j];
-    }
-    for (int i = threadIdx.x; i < kBoysNT; i += blockDim.x) etab[i] = a.bexp[i];
-    __syncthreads();
+    load_boys_table<L>(a, tab, etab);
     const int lane = threadIdx.x & 63;
     const int ns = a.nshell;
     unsigned long long cnt_q = 0, cnt_t = 0;
@@ -228,6 +345,15 @@ void k_sr_jk(SRArgs a)
 #pragma unroll
                     for (int i3 = 0; i3 < ND; ++i3) acc[i0][i1][i2][i3] = 0.0;
         unsigned long long ent_terms = 0;
+        // the nearest lattice translate of the group centres' difference
+        double S[3];
+        {
+            const double cg[3] = {gb.C[0] - gk.C[0], gb.C[1] - gk.C[1], gb.C[2] - gk.C[2]};
+            double n[3];
+            nearest_translate(a.lat, cg, n);
+#pragma unroll
+            for (int x = 0; x < 3; ++x) S[x] = n[0] * a.lat.M[x] + n[1] * a.lat.M[3 + x] + n[2] * a.lat.M[6 + x];
+        }
         // Ket pairs outer (each lane reads its own ket records once), bra pairs
         // inner.  A group's pairs are stored by descending Q, so the first pair
         // that fails the Cauchy-Schwarz test ends its loop.  When every lane of
@@ -239,93 +365,8 @@ void k_sr_jk(SRArgs a)
             for (int pk = gk.pstart; pk < pk_end; ++pk) {
                 const PairRec Pk = a.pairs[pk];
                 if (!(gb.Qmax * Pk.Q * wD > a.d_schwarz)) break;
-                EAxis<LC, LD> Fx, Fy, Fz;
-                const double hk = 0.5 * Pk.pad[0];
-                herm_axis<LC, LD>(hk, Pk.PA[0], Pk.PB[0], Fx);
-                herm_axis<LC, LD>(hk, Pk.PA[1], Pk.PB[1], Fy);
-                herm_axis<LC, LD>(hk, Pk.PA[2], Pk.PB[2], Fz);
-                for (int pb = pbs; pb < pbe; ++pb) {
-                    const PairRec Pb = load_pair(bpairs + pb);
-                    if (!(Pb.Q * Pk.Q * wD > a.d_schwarz)) break;
-                    ++cnt_q;
-                    double rad2;
-                    if (!quartet_sphere(Pb, Pk, a.w2, a.d_ewald_R, rad2)) continue;
-                    const double p = Pb.p, q = Pk.p;
-                    const double rho = fast_rcp(Pb.pad[0] + Pk.pad[0]);
-                    const double pref = Pb.cpre * Pk.cpre * kTwoPi52 * Pb.pad[0] * Pk.pad[0] * fast_rsqrt(p + q);
-                    EAxis<LA, LB> Ex, Ey, Ez;
-                    const double hb = 0.5 * Pb.pad[0];
-                    herm_axis<LA, LB>(hb, Pb.PA[0], Pb.PB[0], Ex);
-                    herm_axis<LA, LB>(hb, Pb.PA[1], Pb.PB[1], Ey);
-                    herm_axis<LA, LB>(hb, Pb.PA[2], Pb.PB[2], Ez);
-                    const double cen[3] = {Pb.P[0] - Pk.P[0], Pb.P[1] - Pk.P[1], Pb.P[2] - Pk.P[2]};
-                    if (FOLD) {
-                        // lattice sum of the Hermite integrals in FP64, one transform
-                        double Rs[L + 1][L + 1][L + 1];
-    #pragma unroll
-                        for (int t = 0; t <= L; ++t)
-    #pragma unroll
-                            for (int u = 0; u <= L - t; ++u)
-    #pragma unroll
-                                for (int v = 0; v <= L - t - u; ++v) Rs[t][u][v] = 0.0;
-                        int nimg = 0;
-                        for_images(a.lat, cen, rad2, a.rcap2, [&](const double *Lv, double L2) {
-                            ++nimg;
-                            if (F32) {
-                                float R0[L + 1];
-                                sr_R0_mixed<L>(rho, a.w2, L2, tab, etab, R0);
-                                float R[L + 1][L + 1][L + 1];
-                                herm_R<L, float>(R0, (float)Lv[0], (float)Lv[1], (float)Lv[2], R);
-    #pragma unroll
-                                for (int t = 0; t <= L; ++t)
-    #pragma unroll
-                                    for (int u = 0; u <= L - t; ++u)
-    #pragma unroll
-                                        for (int v = 0; v <= L - t - u; ++v) Rs[t][u][v] += (double)R[t][u][v];
-                            } else {
-                                double R0[L + 1];
-                                sr_R0<L, kBoysTerms, true>(rho, a.w2, L2, tab, etab, R0);
-                                double R[L + 1][L + 1][L + 1];
-                                herm_R<L, double>(R0, Lv[0], Lv[1], Lv[2], R);
-    #pragma unroll
-                                for (int t = 0; t <= L; ++t)
-    #pragma unroll
-                                    for (int u = 0; u <= L - t; ++u)
-    #pragma unroll
-                                        for (int v = 0; v <= L - t - u; ++v) Rs[t][u][v] += R[t][u][v];
-                            }
-                        });
-                        if (nimg == 0) continue;
-                        cnt_t += nimg;
-                        ent_terms += nimg;
-                        V Rv[L + 1][L + 1][L + 1];
-    #pragma unroll
-                        for (int t = 0; t <= L; ++t)
-    #pragma unroll
-                            for (int u = 0; u <= L - t; ++u)
-    #pragma unroll
-                                for (int v = 0; v <= L - t - u; ++v) Rv[t][u][v] = (V)Rs[t][u][v];
-                        add_term<LA, LB, LC, LD, V, IC0, NIC>(Ex, Ey, Ez, Fx, Fy, Fz, Rv, pref, acc);
-                    } else {
-                        for_images(a.lat, cen, rad2, a.rcap2, [&](const double *Lv, double L2) {
-                            ++cnt_t;
-                            ++ent_terms;
-                            if (F32) {
-                                float R0[L + 1];
-                                sr_R0_mixed<L>(rho, a.w2, L2, tab, etab, R0);
-                                float R[L + 1][L + 1][L + 1];
-                                herm_R<L, float>(R0, (float)Lv[0], (float)Lv[1], (float)Lv[2], R);
-                                add_term<LA, LB, LC, LD, float, IC0, NIC>(Ex, Ey, Ez, Fx, Fy, Fz, R, pref, acc);
-                            } else {
-                                double R0[L + 1];
-                                sr_R0<L, kBoysTerms, true>(rho, a.w2, L2, tab, etab, R0);
-                                double R[L + 1][L + 1][L + 1];
-                                herm_R<L, double>(R0, Lv[0], Lv[1], Lv[2], R);
-                                add_term<LA, LB, LC, LD, double, IC0, NIC>(Ex, Ey, Ez, Fx, Fy, Fz, R, pref, acc);
-                            }
-                        });
-                    }
-                }
+                bra_sweep<LA, LB, LC, LD, V, FOLD, IC0, NIC>(a, bpairs, pbs, pbe, Pk, wD, S, tab, etab, acc, cnt_q,
+                                                            cnt_t, ent_terms);
             }
         };
         const int bi0 = __builtin_amdgcn_readfirstlane(bi);
@@ -354,20 +395,28 @@ void k_sr_jk(SRArgs a)
     }
 }
 
-// One launch per slice of NIC components of the first ket shell.
-template <int LA, int LB, int LC, int LD, int NIC, int IC0 = 0>
-hipError_t launch_slices(const SRArgs &a, bool fold, hipStream_t st)
+// One launch per slice of NIC components of the first ket shell, in the
+// value type V of the work list.
+template <int LA, int LB, int LC, int LD, int NIC, typename V, int IC0 = 0>
+hipError_t launch_slices_v(const SRArgs &a, bool fold, hipStream_t st)
 {
     if constexpr (IC0 >= ncart(LC)) {
         return hipSuccess;
     } else {
         const dim3 g((unsigned)std::max(1L, (a.max_entries + 255) / 256)), b(256);
-        if (fold) hipLaunchKernelGGL((k_sr_jk<LA, LB, LC, LD, double, true, IC0, NIC>), g, b, 0, st, a);
-        else hipLaunchKernelGGL((k_sr_jk<LA, LB, LC, LD, double, false, IC0, NIC>), g, b, 0, st, a);
+        if (fold) hipLaunchKernelGGL((k_sr_jk<LA, LB, LC, LD, V, true, IC0, NIC>), g, b, 0, st, a);
+        else hipLaunchKernelGGL((k_sr_jk<LA, LB, LC, LD, V, false, IC0, NIC>), g, b, 0, st, a);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        return launch_slices<LA, LB, LC, LD, NIC, IC0 + NIC>(a, fold, st);
+        return launch_slices_v<LA, LB, LC, LD, NIC, V, IC0 + NIC>(a, fold, st);
     }
+}
+
+template <int LA, int LB, int LC, int LD, int NIC>
+hipError_t launch_slices(const SRArgs &a, bool f32, bool fold, hipStream_t st)
+{
+    return f32 ? launch_slices_v<LA, LB, LC, LD, NIC, float>(a, fold, st)
+               : launch_slices_v<LA, LB, LC, LD, NIC, double>(a, fold, st);
 }
 
 }  // namespace

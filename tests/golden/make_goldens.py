@@ -12,8 +12,9 @@ Files (symmetric matrices are stored as their upper triangles, row-major):
                   bra shells of atom 0 (an s, a p and the d shell) of the
                   real-space part and of the reciprocal + self parts of J, K
   cfg2_full.npz   64-water workload (nbf 832, delta 1e-10): J, K, E_J, E_K
-  serve_reqs.npz  serving requests 0, 1 and 3 (H/C/O with d shells; nbf 274,
-                  304, 110): J, K, E_J, E_K of each
+  serve_reqs.npz  serving requests 4 and 7 (H/C/O with d shells, nbf 45 and
+                  63) in full (J, K, E_J, E_K) and request 1 (nbf 304, the
+                  largest of the first thirteen) on the rows of three shells
 """
 import os
 import sys
@@ -29,7 +30,9 @@ from paper_2410_22278_amd import inputs  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CFG4_SHELLS = [0, 2, 4]
-SERVE_IDS = [0, 1, 3]
+# serving requests: the two smallest with a C atom (d shells) in full, and the
+# largest of the first thirteen on the rows of an H s, an O p and a C d shell
+SERVE = [(4, None), (7, None), (1, [0, 7, 17])]
 
 
 def upper(M):
@@ -73,20 +76,30 @@ def cfg2():
 
 def serve():
     rec = {}
-    for i in SERVE_IDS:
+    done = []
+    out = os.path.join(HERE, "serve_reqs.npz")
+    for i, shells in SERVE:
         s = inputs.serving_request(i)
         t0 = time.time()
         # FP64 oracle of the same cell (the request itself runs mixed precision)
-        r = oracle.jk(s)
-        print(f"request {i}: natom {s.natom} nbf {s.nbf}: {time.time() - t0:.0f} s", flush=True)
+        r = oracle.jk(s, bra_shells=shells)
+        print(f"request {i}: natom {s.natom} nbf {s.nbf} {'rows of shells %s' % shells if shells else 'full'}: "
+              f"{time.time() - t0:.0f} s", flush=True)
         rec[f"n_{i}"] = s.nbf
-        rec[f"J_{i}"] = upper(r["J"])
-        rec[f"K_{i}"] = upper(r["K"])
-        rec[f"E_J_{i}"] = r["E_J"]
-        rec[f"E_K_{i}"] = r["E_K"]
-    out = os.path.join(HERE, "serve_reqs.npz")
-    np.savez_compressed(out, ids=np.array(SERVE_IDS), **rec)
-    print(f"wrote {out}", flush=True)
+        if shells is None:
+            rec[f"J_{i}"] = upper(r["J"])
+            rec[f"K_{i}"] = upper(r["K"])
+            rec[f"E_J_{i}"] = r["E_J"]
+            rec[f"E_K_{i}"] = r["E_K"]
+        else:
+            rows = np.asarray(r["rows"], dtype=np.int64)
+            rec[f"rows_{i}"] = rows
+            rec[f"J_{i}"] = r["J"][rows]
+            rec[f"K_{i}"] = r["K"][rows]
+        done.append(i)
+        # written after every request, so that a long run leaves the finished ones
+        np.savez_compressed(out, ids=np.array(done), **rec)
+        print(f"wrote {out} (requests {done})", flush=True)
 
 
 if __name__ == "__main__":

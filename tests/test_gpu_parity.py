@@ -140,13 +140,15 @@ MIXED = [
 
 
 @pytest.mark.parametrize("case", MIXED, ids=["mixed5", "mixed13"])
-def test_mixed_precision_small(lib, oracle_mod, case):
+def test_mixed_precision_small(lib, oracle_mod, case, monkeypatch):
     """FP32 for every quartet whose density-weighted bound is below 4e-3
     (most of them, to exercise the single-precision path) against the FP64
     oracle: stated tolerances 1e-7 for matrix elements, 1e-6 Eh/atom.  (The
     short-range Cauchy-Schwarz factors carry the erfc kernel's sqrt(1 - c),
     so 4e-3 puts about the quartets in FP32 that 1e-2 did with the Coulomb
-    s-type factor.)"""
+    s-type factor.)  PBCJK_FP32_MIN_L=0 splits every class pair, so that the
+    s and p FP32 kernels run too."""
+    monkeypatch.setenv("PBCJK_FP32_MIN_L", "0")
     s = inputs.small_cell(**case)
     ref = oracle_mod.jk(s)
     thr = Thresholds(**{**s.thr.__dict__, "fp32_below": 4e-3})
@@ -278,7 +280,9 @@ def test_j_only_cfg1_and_cfg2_rows(lib, oracle_mod):
     print(f"J-only cfg1 max|dJ|={d1:.3e} dE_J={EJ1 - ref1['E_J']:.3e}; cfg2 rows max|dJ|={d2:.3e}, "
           f"short range {st['t_sr_ms']:.1f} ms, build {st['t_build_ms']:.1f} ms", flush=True)
     assert d1 < 1e-9 and abs(EJ1 - ref1["E_J"]) < 1e-9 and d2 < 1e-9
-    # every class pair of the s/p cell ran the J-engine
-    for k in range(21):
+    # every class pair of the s/p cell whose bra is not an s-s pair ran the
+    # J-engine; the (ss|..) ones ran the fused kernel
+    slots = [(cb, ck) for cb in range(6) for ck in range(cb, 6)]
+    for k, (cb, ck) in enumerate(slots):
         if st["terms_class"][k] > 0:
-            assert (st["sr_jengine_mask"] >> k) & 1, k
+            assert bool((st["sr_jengine_mask"] >> k) & 1) == (cb >= 1), k
