@@ -88,6 +88,12 @@ struct pbc_jk {
     // build work space
     double *d_D = nullptr, *d_Dt = nullptr, *d_Dmax = nullptr, *d_X = nullptr, *d_Y = nullptr;
     double *d_Jt = nullptr, *d_Kt = nullptr, *d_F = nullptr, *d_T = nullptr, *d_rho = nullptr;
+    // The structure-factor kernels overwrite every block of the shell pairs
+    // in the pair list and nothing else writes F, so once the handle's own F
+    // has been cleared the blocks of absent shell pairs stay zero: f_clean is
+    // the buffer known to be in that state (a buffer lent by the static
+    // entry point is cleared at every use).
+    const double *f_clean = nullptr, *f_own = nullptr;
     double *d_scal = nullptr, *d_Jo = nullptr, *d_Ko = nullptr;
     unsigned long long *d_dmaxg = nullptr, *d_cnt = nullptr;
     unsigned long long *stat_cnt = nullptr;   // counters of the last build (own or scratch buffer)
@@ -106,6 +112,7 @@ struct pbc_jk {
     hipEvent_t ev_ctl = nullptr; // recorded after that copy
     int lr_cap = 0;              // columns queued for the last factor (upper bound of its rank)
     int y_tile = 64;             // output tile of the products Y_b^T = L^T F_b
+    int gemm_grid = 0;           // > 0: workgroups of the low-rank exchange products (else one a tile)
     // stream capture of the host-memory build: the device work of one build
     // (D in d_D to J, K in d_Jo, d_Ko and the energies in d_scal) as a graph
     bool use_graph = false, capturing = false;
@@ -209,7 +216,8 @@ int upload(pbc_jk *h, T **p, const std::vector<T> &v)
 void release_device(pbc_jk *h)
 {
     void **pp[] = {(void **)&h->d_pairs, (void **)&h->d_groups, (void **)&h->d_boys, (void **)&h->d_bexp, (void **)&h->d_S,
-                   (void **)&h->d_G, (void **)&h->d_Gw, (void **)&h->d_Gs, (void **)&h->d_sp_start, (void **)&h->d_sp_pairs,
+                   (void **)&h->d_G, (void **)&h->d_Gw, (void **)&h->d_Gs,
+                   (void **)&h->d_sp_start, (void **)&h->d_sp_pairs,
                    (void **)&h->d_sp_shA, (void **)&h->d_sp_shB, (void **)&h->d_sh_l, (void **)&h->d_sh_aoc,
                    (void **)&h->d_tr_ao, (void **)&h->d_inv_ci, (void **)&h->d_tr_c, (void **)&h->d_dscale,
                    (void **)&h->d_inv_cc, (void **)&h->d_D, (void **)&h->d_Dt, (void **)&h->d_Dmax,
@@ -226,6 +234,7 @@ void release_device(pbc_jk *h)
     }
     h->dev_bytes = 0;
     h->timed = false;
+    h->f_clean = h->f_own = nullptr;
 }
 
 void drop_graph(pbc_jk *h);
@@ -384,6 +393,7 @@ int create_device(pbc_jk *h)
     }
     // reciprocal-space chunk: F and T hold 2 * gchunk matrices each
     if (const char *e = std::getenv("PBCJK_Y_TILE")) h->y_tile = std::atoi(e) == 128 ? 128 : 64;
+    if (const char *e = std::getenv("PBCJK_GEMM_GRID")) h->gemm_grid = std::max(0, std::atoi(e));
     if (const char *e = std::getenv("PBCJK_COOP_RATIO")) h->coop_ratio = std::max(0.0, std::atof(e));
     if (const char *e = std::getenv("PBCJK_FP32_MIN_L")) h->fp32_min_l = std::max(0, std::atoi(e));
     const int nG = (int)S.Gw.size();
@@ -392,6 +402,8 @@ int create_device(pbc_jk *h)
     long per = (long)(budget_mb * 1048576.0 / (4.0 * 8.0 * (double)n2));
     h->gchunk = (int)std::max(1L, std::min<long>(per, std::max(nG, 1)));
     if ((rc = dalloc(h, &h->d_F, 2 * (size_t)h->gchunk * n2))) return rc;
+    h->f_own = h->d_F;
+    h->f_clean = nullptr;
     if ((rc = dalloc(h, &h->d_T, std::max<size_t>(2 * (size_t)h->gchunk * n2, n2)))) return rc;
     if ((rc = dalloc(h, &h->d_rho, 2 * (size_t)h->gchunk))) return rc;
     const int n = S.nbfc, nblk = (n + 63) / 64;
@@ -565,6 +577,7 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
         a.rcap2 = S.r_cut > 0 ? S.r_cut * S.r_cut : 0.0;
         a.fp32_below = S.fp32_below;
         a.boys = h->d_boys; a.bexp = h->d_bexp; a.counters = h->d_cnt;
+        a.want_k = wantK ? 1 : 0;
         int slot = 0;
         for (int cb = 0; cb < kNumClass; ++cb)
             for (int ck = cb; ck < kNumClass; ++ck, ++slot) {
@@ -644,7 +657,11 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
     // structure factors of one chunk of reciprocal vectors into F, then their
     // J contribution
     auto sfac_j = [&](int g0, int gc, hipStream_t s) -> int {
-        HIPCHK(launch_fill(h->d_F, 2L * gc * n2, 0.0, s));
+        if (h->d_F != h->f_clean) {
+            HIPCHK(launch_fill(h->d_F, 2L * gc * n2, 0.0, s));
+            // the first chunk is the largest: later chunks stay inside the cleared part
+            if (g0 == 0 && h->d_F == h->f_own) h->f_clean = h->d_F;
+        }
         sa.G = h->d_G + 3 * g0; sa.Gs = h->d_Gs + g0; sa.ng = gc;
         {
             TimedLaunch tl(h, s, 1, 0.0);
@@ -730,6 +747,7 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
                 g1.C = h->d_T; g1.ldc = n; g1.sC = (long)n * cap;
                 g1.nbatch = nb; g1.alpha0 = 1.0; g1.reduce = 0; g1.slices = 1;
                 g1.ctl = h->d_ctl; g1.ctl_mode = 4; g1.role = 2; g1.tile = h->y_tile;
+                g1.grid_cap = h->gemm_grid;
                 {
                     TimedLaunch tl(h, ls, 30, 2.0 * nd * nd * nb);   // per unit of rank
                     HIPCHK(launch_dgemm(g1, ls));
@@ -744,6 +762,7 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
                 g2.nbatch = nb; g2.alpha0 = 1.0; g2.reduce = 1; g2.upper = 1;
                 g2.slices = (int)std::max(1L, std::min<long>(nb, (kStage2Blocks + upper_tiles - 1) / upper_tiles));
                 g2.ctl = h->d_ctl; g2.ctl_mode = 2; g2.role = 3;
+                g2.grid_cap = h->gemm_grid;
                 {
                     TimedLaunch tl(h, ls, 31, nd * (nd + 1.0) * nb);   // per unit of rank (upper triangle)
                     HIPCHK(launch_dgemm(g2, ls));
@@ -1169,7 +1188,7 @@ int pbc_jk_one_electron(pbc_jk *h, double *S_out, double *T_out, double *V_out, 
         sa.pairs = h->d_pairs; sa.sp_start = h->d_sp_start; sa.sp_pairs = h->d_sp_pairs;
         sa.sp_shA = h->d_sp_shA; sa.sp_shB = h->d_sp_shB; sa.sh_l = h->d_sh_l; sa.sh_aoc = h->d_sh_aoc;
         sa.F = h->d_F; sa.nbfc = n;
-        for (int g0 = 0; g0 < nG; g0 += h->gchunk) {
+            for (int g0 = 0; g0 < nG; g0 += h->gchunk) {
             const int gc = std::min(h->gchunk, nG - g0);
             sa.G = h->d_G + 3 * g0; sa.Gs = h->d_Gs + g0; sa.ng = gc;
             HIPCHK(launch_fill(h->d_F, 2L * gc * n2, 0.0, st));

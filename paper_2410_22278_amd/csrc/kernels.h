@@ -30,6 +30,7 @@ struct SRArgs {
                                     // [2 + slot] terms of this class pair, [23] FP32 terms,
                                     // [24 + slot] primitive quartets of this class pair
     int slot;             // class-pair index (0..20)
+    int want_k;           // 0: builds without K skip the K half's contractions and atomics
     // J-engine only: Hermite densities of the bra and ket classes' pairs, the
     // densities of pair k at hd + (k - hd_p0) n_h(l_a + l_b)
     const double *hd_b, *hd_k;
@@ -178,6 +179,8 @@ struct GemmArgs {
     int role;
     int tile;             // output tile edge, 64 or 128 (0: kGemmTile); products that
                           // accumulate the upper tiles of K always use kGemmTile
+    int grid_cap;         // > 0: at most this many workgroups (a multiple of 8), each
+                          // striding over the tiles
 };
 hipError_t launch_dgemm(const GemmArgs &a, hipStream_t st);
 // Edge of the upper blocks in which K is accumulated (and read back by the

@@ -769,7 +769,9 @@ hipError_t launch_dgemm_t(const GemmArgs &a, hipStream_t st)
     // one tile per workgroup, except for products that run only when the
     // device-side decision falls back to them: a capped persistent grid, so
     // that the usual case (gated off) costs few workgroups
-    dim3 grid((unsigned)(a.ctl_mode == 3 ? std::min(tiles, kGemmGrid) : tiles));
+    long blocks = a.ctl_mode == 3 ? std::min(tiles, kGemmGrid) : tiles;
+    if (a.grid_cap > 0) blocks = std::min(blocks, (long)(a.grid_cap + 7) / 8 * 8);
+    dim3 grid((unsigned)blocks);
     switch (a.role) {
         case 1: hipLaunchKernelGGL((k_dgemm<1, T>), grid, dim3(256), 0, st, a); break;
         case 2: hipLaunchKernelGGL((k_dgemm<2, T>), grid, dim3(256), 0, st, a); break;

@@ -122,6 +122,7 @@ __device__ __forceinline__ void scatter_block(const SRArgs &a, const double (&ac
                 for (int ib = 0; ib < NB; ++ib) s += acc[ia][ib][ic][id] * Dt[(aoA + ia) * n + aoB + ib];
             atomicAdd(&a.X[(aoC + ic) * n + aoD + id], 2.0 * w * s);
         }
+    if (!a.want_k) return;   // builds without K: the J targets only
 #pragma unroll
     for (int ia = 0; ia < NA; ++ia)
 #pragma unroll
