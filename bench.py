@@ -150,7 +150,7 @@ def serve(args, np, torch, inputs, pbcjk):
           f"nbf {min(r.nbf for r in reqs)}-{max(r.nbf for r in reqs)}", file=sys.stderr, flush=True)
 
     def run(arrivals):
-        with pbcjk.Server(slots=4, cache_cells=False) as srv:
+        with pbcjk.Server(slots=4, cache_cells=False, policy=args.policy) as srv:
             t0 = time.perf_counter()
             tickets = [None] * len(reqs)
 
@@ -162,14 +162,21 @@ def serve(args, np, torch, inputs, pbcjk):
                     tickets[i] = srv.submit(r)
             th = threading.Thread(target=feeder)
             th.start()
-            res = []
-            for i in range(len(reqs)):
+            # wait in the order the requests are expected to finish (the
+            # server's queue order), so that progress is reported as it happens
+            if args.policy == "deadline":
+                order = sorted(range(len(reqs)), key=lambda i: arrivals[i] + 6.8e-6 * reqs[i].nbf ** 2)
+            else:
+                order = list(range(len(reqs)))
+            res = [None] * len(reqs)
+            last = time.perf_counter()
+            for done, i in enumerate(order, 1):
                 while tickets[i] is None:
                     time.sleep(0.01)
-                res.append(srv.wait(tickets[i]))
-                if (i + 1) % 32 == 0:
-                    print(f"  {i + 1}/{len(reqs)} requests done, {time.perf_counter() - t0:.1f} s", file=sys.stderr,
-                          flush=True)
+                res[i] = srv.wait(tickets[i])
+                if done % 16 == 0 or time.perf_counter() - last > 30.0:
+                    last = time.perf_counter()
+                    print(f"  {done}/{len(reqs)} requests done, {last - t0:.1f} s", file=sys.stderr, flush=True)
             th.join()
             wall = time.perf_counter() - t0
             st = srv.stats()
@@ -192,7 +199,7 @@ def serve(args, np, torch, inputs, pbcjk):
         "steps": len(reqs), "warmup": 0, "ms_per_step": 1000.0 * wall / len(reqs), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
         "config": {"workload": f"cfg5: {WORKLOADS['cfg5']}", "requests": len(reqs),
-                   "arrival_rate_per_s": rate, "saturated_builds_per_s": sat,
+                   "arrival_rate_per_s": rate, "saturated_builds_per_s": sat, "queue_policy": args.policy,
                    "precision": "mixed (fp32 below 1e-06)"},
         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
         "build_ms_p50": float(np.percentile(build, 50)), "build_ms_max": float(build.max()),
@@ -390,6 +397,8 @@ def main():
     ap.add_argument("--no-cfg4", action="store_true", help="headline: leave out the cfg4 legs")
     ap.add_argument("--requests", type=int, default=256, help="cfg5: requests of the stream to run")
     ap.add_argument("--rate-factor", type=float, default=0.8, help="cfg5: arrival rate / saturated rate")
+    ap.add_argument("--policy", default="deadline", choices=["arrival", "deadline"],
+                    help="cfg5: the request server's queue order")
     ap.add_argument("--parts", default="all", choices=["all", "sr", "lr", "self", "lr+self"],
                     help="build only these parts of J and K (profiling one stream alone); the line then "
                          "reports that partial build and no legs")

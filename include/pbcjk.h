@@ -289,8 +289,9 @@ int pbc_jk_set_lr(pbc_jk *h, int mode, double tol);
  * arena of `hbm_budget` bytes allocated at creation (no hipMalloc/hipFree per
  * request).  A request for a new cell is admitted when its footprint (setup
  * data, work buffers and neighbour lists) fits in the free part of the arena;
- * the first new-cell request that does not fit blocks later new-cell
- * requests (no starvation), while requests for cells already resident run
+ * the first new-cell request (in queue order, see `policy`) that does not
+ * fit blocks later new-cell requests (no starvation), while requests for
+ * cells already resident run
  * as soon as their cell is idle.  With cache_cells set, a cell's setup data
  * stays resident after its build and later requests with identical cell,
  * atoms, basis, omega and thresholds reuse it; idle cells are evicted
@@ -307,7 +308,15 @@ typedef struct {
     double lr_budget_mb;  /* per-cell reciprocal-sum chunk budget; 0 = 1024 MB              */
     int use_graphs;       /* with cache_cells: builds of a resident cell after its first one
                              replay a captured HIP graph (pbc_jk_set_graph)                 */
+    int policy;           /* queue order: PBC_JK_SERVE_ARRIVAL (0) by submission;
+                             PBC_JK_SERVE_DEADLINE (1) by submission time plus an estimate
+                             of the build time from the cell's AO count (c nbf^2), so that
+                             small requests pass large ones queued a little earlier while
+                             every request still comes first once it has waited its own
+                             estimate longer than later arrivals                            */
 } pbc_jk_server_config;
+#define PBC_JK_SERVE_ARRIVAL 0
+#define PBC_JK_SERVE_DEADLINE 1
 
 typedef struct {
     int status;           /* 0 or the request's error code                                  */

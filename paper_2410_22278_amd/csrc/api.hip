@@ -112,7 +112,6 @@ struct pbc_jk {
     hipEvent_t ev_ctl = nullptr; // recorded after that copy
     int lr_cap = 0;              // columns queued for the last factor (upper bound of its rank)
     int y_tile = 64;             // output tile of the products Y_b^T = L^T F_b
-    int gemm_grid = 0;           // > 0: workgroups of the low-rank exchange products (else one a tile)
     // stream capture of the host-memory build: the device work of one build
     // (D in d_D to J, K in d_Jo, d_Ko and the energies in d_scal) as a graph
     bool use_graph = false, capturing = false;
@@ -393,7 +392,6 @@ int create_device(pbc_jk *h)
     }
     // reciprocal-space chunk: F and T hold 2 * gchunk matrices each
     if (const char *e = std::getenv("PBCJK_Y_TILE")) h->y_tile = std::atoi(e) == 128 ? 128 : 64;
-    if (const char *e = std::getenv("PBCJK_GEMM_GRID")) h->gemm_grid = std::max(0, std::atoi(e));
     if (const char *e = std::getenv("PBCJK_COOP_RATIO")) h->coop_ratio = std::max(0.0, std::atof(e));
     if (const char *e = std::getenv("PBCJK_FP32_MIN_L")) h->fp32_min_l = std::max(0, std::atoi(e));
     const int nG = (int)S.Gw.size();
@@ -747,7 +745,6 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
                 g1.C = h->d_T; g1.ldc = n; g1.sC = (long)n * cap;
                 g1.nbatch = nb; g1.alpha0 = 1.0; g1.reduce = 0; g1.slices = 1;
                 g1.ctl = h->d_ctl; g1.ctl_mode = 4; g1.role = 2; g1.tile = h->y_tile;
-                g1.grid_cap = h->gemm_grid;
                 {
                     TimedLaunch tl(h, ls, 30, 2.0 * nd * nd * nb);   // per unit of rank
                     HIPCHK(launch_dgemm(g1, ls));
@@ -762,7 +759,6 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
                 g2.nbatch = nb; g2.alpha0 = 1.0; g2.reduce = 1; g2.upper = 1;
                 g2.slices = (int)std::max(1L, std::min<long>(nb, (kStage2Blocks + upper_tiles - 1) / upper_tiles));
                 g2.ctl = h->d_ctl; g2.ctl_mode = 2; g2.role = 3;
-                g2.grid_cap = h->gemm_grid;
                 {
                     TimedLaunch tl(h, ls, 31, nd * (nd + 1.0) * nb);   // per unit of rank (upper triangle)
                     HIPCHK(launch_dgemm(g2, ls));

@@ -179,8 +179,6 @@ struct GemmArgs {
     int role;
     int tile;             // output tile edge, 64 or 128 (0: kGemmTile); products that
                           // accumulate the upper tiles of K always use kGemmTile
-    int grid_cap;         // > 0: at most this many workgroups (a multiple of 8), each
-                          // striding over the tiles
 };
 hipError_t launch_dgemm(const GemmArgs &a, hipStream_t st);
 // Edge of the upper blocks in which K is accumulated (and read back by the

@@ -131,7 +131,12 @@ struct Request {
     size_t dev_bytes = 0;
     pbc_jk *prepared = nullptr;  // host setup done, device part not yet created
     size_t fixed = 0, need = 0;  // device bytes: without / with the neighbour lists
+    double key = 0.0;            // queue order (ascending)
 };
+
+// Estimated build seconds per squared AO: about 16 s for the largest serving
+// cells (nbf ~ 1500) and 0.6 s at nbf ~ 300 on one MI355X.
+constexpr double kBuildSecPerNbf2 = 6.8e-6;
 
 }  // namespace
 
@@ -141,7 +146,8 @@ struct pbc_jk_server {
     Arena arena;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
-    std::deque<Request *> queue;  // ascending id
+    std::deque<Request *> queue;  // ascending key
+    Clock::time_point t0 = Clock::now();
     std::unordered_map<unsigned long long, Request *> reqs;
     std::unordered_map<std::string, Cell *> cells;
     std::vector<std::thread> workers;
@@ -188,12 +194,19 @@ pbc_jk *drop_placeholder(pbc_jk_server *s, Request *r)
     return h;
 }
 
+// Inserts by key (ties by id), so the queue stays in the policy's order.
+void enqueue(pbc_jk_server *s, Request *r)
+{
+    auto it = std::lower_bound(s->queue.begin(), s->queue.end(), r, [](const Request *a, const Request *b) {
+        return a->key < b->key || (a->key == b->key && a->id < b->id);
+    });
+    s->queue.insert(it, r);
+}
+
 void requeue(pbc_jk_server *s, Request *r)
 {
     r->state = RState::Queued;
-    auto it = std::lower_bound(s->queue.begin(), s->queue.end(), r,
-                               [](const Request *a, const Request *b) { return a->id < b->id; });
-    s->queue.insert(it, r);
+    enqueue(s, r);
 }
 
 // Evicts idle resident cells, least recently used first, until `need` bytes
@@ -438,6 +451,10 @@ int pbc_jk_server_create(const pbc_jk_server_config *cfg, pbc_jk_server **out)
     if (!s) return PBC_JK_ENOMEM;
     if (cfg) s->cfg = *cfg;
     if (s->cfg.slots <= 0) s->cfg.slots = 4;
+    if (s->cfg.policy != PBC_JK_SERVE_ARRIVAL && s->cfg.policy != PBC_JK_SERVE_DEADLINE) {
+        delete s;
+        return PBC_JK_EINVAL;
+    }
     if (s->cfg.slots > 64) {
         delete s;
         return PBC_JK_EINVAL;
@@ -521,8 +538,12 @@ int pbc_jk_server_submit(pbc_jk_server *s, const pbc_cell *cell, const pbc_atoms
             return PBC_JK_EINVAL;
         }
         r->id = s->next_id++;
+        r->key = s->cfg.policy == PBC_JK_SERVE_DEADLINE
+                     ? std::chrono::duration<double>(r->t_submit - s->t0).count() +
+                           kBuildSecPerNbf2 * (double)nbf * (double)nbf
+                     : (double)r->id;
         s->reqs[r->id] = r;
-        s->queue.push_back(r);
+        enqueue(s, r);
         s->c.submitted++;
         *ticket = r->id;
     }

@@ -23,6 +23,7 @@ PBC_JK_ENOTSUP = -4
 PBC_JK_ECANCELED = -5
 PBC_JK_EBUSY = -6
 PART_SR, PART_LR, PART_SELF = 1, 2, 4
+SERVE_ARRIVAL, SERVE_DEADLINE = 0, 1
 LR_AUTO, LR_DENSE = 0, 1
 
 # every symbol the header declares
@@ -68,7 +69,7 @@ class pbc_jk_counters(ctypes.Structure):
 
 class pbc_jk_server_config(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("slots", c_int), ("cache_cells", c_int),
-                ("lr_budget_mb", c_double), ("use_graphs", c_int)]
+                ("lr_budget_mb", c_double), ("use_graphs", c_int), ("policy", c_int)]
 
 
 class pbc_jk_request_info(ctypes.Structure):
@@ -383,10 +384,11 @@ class Server:
     the ticket is waited for."""
 
     def __init__(self, hbm_budget: int = 0, slots: int = 4, cache_cells: bool = True,
-                 lr_budget_mb: float = 0.0, use_graphs: bool = False):
+                 lr_budget_mb: float = 0.0, use_graphs: bool = False, policy: str = "arrival"):
         lib = load()
+        pol = {"arrival": SERVE_ARRIVAL, "deadline": SERVE_DEADLINE}[policy]
         cfg = pbc_jk_server_config(int(hbm_budget), int(slots), 1 if cache_cells else 0, float(lr_budget_mb),
-                                   1 if use_graphs else 0)
+                                   1 if use_graphs else 0, pol)
         s = c_void_p()
         _check(lib.pbc_jk_server_create(byref(cfg), byref(s)))
         self.s = s.value

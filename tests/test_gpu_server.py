@@ -169,3 +169,27 @@ def test_cancel_second_request_of_same_cell(lib, alone, cache):
     assert st["failed"] == 0
     if not cache:
         assert st["in_use"] == 0
+
+
+@pytest.mark.parametrize("policy", ["arrival", "deadline"])
+def test_queue_policy(lib, alone, policy):
+    """One slot, a running build, then a large and a small request queued
+    behind it: in arrival order the large one runs first; with the deadline
+    order (submission time plus c nbf^2) the small one passes it.  Both
+    results stay those of the builds alone."""
+    blocker, big, small = 12, 1, 4
+    with lib.Server(slots=1, cache_cells=False, policy=policy) as srv:
+        tb = srv.submit(alone[blocker][0])
+        tl = srv.submit(alone[big][0])
+        ts = srv.submit(alone[small][0])
+        rb, rl, rs = srv.wait(tb), srv.wait(tl), srv.wait(ts)
+    for r in (rb, rl, rs):
+        assert r["status"] == 0, r.get("error")
+    print(f"policy {policy}: large queue {rl['queue_ms']:.1f} ms, small queue {rs['queue_ms']:.1f} ms", flush=True)
+    if policy == "arrival":
+        assert rs["queue_ms"] > rl["queue_ms"]
+    else:
+        assert rs["queue_ms"] < rl["queue_ms"]
+    for i, r in ((big, rl), (small, rs)):
+        _, J, K, _, _ = alone[i]
+        assert np.abs(r["J"] - J).max() < 1e-10 and np.abs(r["K"] - K).max() < 1e-10
