@@ -5,7 +5,7 @@ of paper_2410_22278_amd.inputs; nothing is read from the GPU library.
 
     python3 tests/golden/make_goldens.py cfg4rows   # ~40 min on 8 cores
     python3 tests/golden/make_goldens.py serve      # ~10 min
-    python3 tests/golden/make_goldens.py cfg2       # ~50 min
+    python3 tests/golden/make_goldens.py cfg2       # ~90 min
 
 Files (symmetric matrices are stored as their upper triangles, row-major):
   cfg4_rows.npz   diamond workload (nbf 6656, delta 1e-11): rows of three
