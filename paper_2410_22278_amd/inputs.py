@@ -346,3 +346,29 @@ def small_cell(seed: int, natom: int = 2, a_ang: float = 3.0, recipe=((0, 0), (1
     nbf = sysm.nbf
     sysm.D = density_from_orbitals(rng, nbf, nocc if nocc else max(1, nbf // 2))
     return sysm
+
+
+# ---------------------------------------------------------------- integration grids
+def atom_grid(xyz, nrad: int = 40, ntheta: int = 12, nphi: int = 24, rscale: float = 1.0):
+    """Atom-centred product grids (inputs of the Becke-weight kernel): per
+    atom, radial Gauss-Legendre nodes x mapped by r = rscale (1 + x)/(1 - x),
+    Gauss-Legendre nodes in cos(theta) and uniform phi.  Returns the points
+    (N x 3), their quadrature weights (r^2 dr dcos(theta) dphi) and the index
+    of each point's origin atom; points are grouped by atom."""
+    xyz = np.asarray(xyz, float)
+    xr, wr = np.polynomial.legendre.leggauss(nrad)
+    r = rscale * (1.0 + xr) / (1.0 - xr)
+    wr = wr * 2.0 * rscale / (1.0 - xr) ** 2 * r * r
+    ct, wt = np.polynomial.legendre.leggauss(ntheta)
+    st = np.sqrt(1.0 - ct * ct)
+    ph = (np.arange(nphi) + 0.5) * (2.0 * np.pi / nphi)
+    wp = 2.0 * np.pi / nphi
+    dirs = np.stack([np.outer(st, np.cos(ph)).ravel(), np.outer(st, np.sin(ph)).ravel(),
+                     np.repeat(ct, nphi)], axis=1)
+    wang = np.repeat(wt, nphi) * wp
+    off = (r[:, None, None] * dirs[None, :, :]).reshape(-1, 3)
+    wq1 = (wr[:, None] * wang[None, :]).ravel()
+    pts = np.concatenate([a + off for a in xyz])
+    wq = np.tile(wq1, len(xyz))
+    origin = np.repeat(np.arange(len(xyz), dtype=np.int32), len(off))
+    return pts, wq, origin
