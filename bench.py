@@ -227,6 +227,47 @@ def oracle_counts(name):
         return None
 
 
+def time_becke(steps, np, torch, inputs, pbcjk, cpu_sample=True):
+    """Periodic Becke weights (the paper's Sec. 2.8 grid partition) of
+    atom-centred product grids on the diamond cell's 512 atoms: 20 radial x
+    8 x 16 angular points per atom (1.31 M points, grouped by atom), 17 bohr
+    sphere, delta 1e-14; points resident in HBM, `steps` timed launches on
+    one stream (HIP events).  The CPU oracle runs a bounded sample."""
+    s4 = inputs.cfg4()
+    pts, wq, org = inputs.atom_grid(s4.xyz, 20, 8, 16, 1.0)
+    with pbcjk.Becke(s4.cell, s4.xyz, rcut=17.0, delta=1e-14) as b:
+        dp = torch.from_numpy(pts).cuda()
+        do = torch.from_numpy(org.astype(np.int32)).cuda()
+        dw = torch.empty(len(pts), dtype=torch.float64, device="cuda")
+        st = torch.cuda.current_stream()
+        b.weights(dp, do, out=dw, stream=st)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(steps):
+            b.weights(dp, do, out=dw, stream=st)
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        w = dw.cpu().numpy()
+        info = b.info()
+    V = abs(float(np.linalg.det(s4.cell)))
+    out = {"workload": "Becke weights: diamond cell (512 atoms, a = 41.05 bohr), 20 x 8 x 16 product grid per atom "
+                       "(1,310,720 points), 17 bohr sphere, delta 1e-14",
+           "steps": steps, "ms_per_launch": ms, "points_per_s": len(pts) / (ms * 1e-3),
+           "images_per_atom": info["max_images"], "sum_w_over_V": float((wq * w).sum()) / V}
+    if cpu_sample:
+        from oracle import becke as obk
+        sel = np.sort(np.random.default_rng(7).choice(len(pts), 512, replace=False))
+        t0 = time.perf_counter()
+        ref = obk.becke_weights(s4.cell, s4.xyz, pts[sel], org[sel], rcut=17.0, delta=1e-14)
+        t = time.perf_counter() - t0
+        out["max_abs_dw_vs_oracle_sample"] = float(np.abs(w[sel] - ref).max())
+        out["cpu_baseline"] = {"value": len(sel) / t, "unit": "points/s", "cores": os.cpu_count(), "kind": "oracle",
+                               "sample": f"{len(sel)} points drawn at random from the grid"}
+    return out
+
+
 def time_workload(system, steps, warmup, np, torch, pbcjk, want_K=True, tag="", parts=None):
     """W untimed builds, then exactly `steps` timed builds through
     pbc_jk_build_device with D resident in HBM.  Returns the timings, the
@@ -297,7 +338,8 @@ def kernel_candidates(acc, steps):
               "ms_per_build": acc["gemm_ms"] / steps, "flops_per_build": acc["gemm_fl"] / steps,
               "launches_per_build": acc["n_gemm"] / steps, "peak": FP64_MFMA_PEAK_TFLOPS}]
     if acc["y_ms"] > 0:
-        cands.append({"kernel": "k_dgemm<2>: low-rank exchange products Y_G^T = L^T F_G", "name": "k_dgemm<2>",
+        yname = "k_ygemm" if st.get("y_kernel", 0) == 1 else "k_dgemm<2>"
+        cands.append({"kernel": f"{yname}: low-rank exchange products Y_G^T = L^T F_G", "name": yname,
                       "bound": "mfma", "ms_per_build": acc["y_ms"] / steps, "flops_per_build": acc["y_fl"] / steps,
                       "launches_per_build": acc["n_y"] / steps, "peak": FP64_MFMA_PEAK_TFLOPS})
     for k in range(21):
@@ -390,7 +432,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="headline", choices=["headline"] + sorted(WORKLOADS),
+    ap.add_argument("--workload", default="headline", choices=["headline", "becke"] + sorted(WORKLOADS),
                     help="headline (default): cfg2 FP64 timed as the line's value, with the cfg3 mixed, "
                          "cfg2 J-only and cfg4 FP64/mixed legs in the same line; or one workload alone")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -431,6 +473,13 @@ def main():
         return
     if args.workload == "cfg5":
         serve(args, np, torch, inputs, pbcjk)
+        return
+    if args.workload == "becke":
+        r = time_becke(args.steps, np, torch, inputs, pbcjk, cpu_sample=not args.no_cpu_baseline)
+        print(json.dumps({"metric": "Becke weights points/s", "value": r["points_per_s"], "unit": "points/s",
+                          "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": r["ms_per_launch"],
+                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+                          "data": "synthetic", "config": {"workload": r["workload"]}, "detail": r}), flush=True)
         return
     name = "cfg2" if args.workload == "headline" else args.workload
     system = inputs.CONFIGS[name]()
@@ -514,6 +563,10 @@ def main():
                           "ms_per_step": aj["ms_per_step"], "fraction_of_jk_build": aj["ms_per_step"] / ms,
                           "vs_oracle": errors_vs_golden("cfg2", system, aj, np)}
         del aj
+        try:
+            legs["becke"] = time_becke(10, np, torch, inputs, pbcjk, cpu_sample=not args.no_cpu_baseline)
+        except Exception as e:   # the J/K line stands without this leg
+            legs["becke"] = {"error": str(e)}
         if not args.no_cfg4:
             est = 200.0     # s: setup, one warm-up and one timed build of the diamond cell
             for key, cname in (("cfg4_fp64", "cfg4"), ("cfg4_mixed", "cfg4m")):

@@ -124,9 +124,10 @@ typedef struct {
     double t_setup_ms;   /* create wall time                                 */
     double t_build_ms;   /* last build wall time                             */
     double t_sr_ms, t_lr_ms, t_other_ms; /* last build, device stage times: density
-                            preparation and short range on the build stream; reciprocal part
-                            and self term on a second stream of the handle, concurrently
-                            with the short range; final assembly after both              */
+                            preparation, the density factor of the low-rank exchange and the
+                            short range on the build stream; reciprocal part and self term on
+                            a second stream of the handle, concurrently with the short range;
+                            final assembly after both                                         */
     double t_gemm_ms;    /* last build: summed durations of the launches of the GEMM kernel that
                             formed the reciprocal exchange (gemm_kernel), self term included
                             when that kernel is the plain one                                  */
@@ -160,6 +161,8 @@ typedef struct {
                             large d pairs)                                                     */
     int sr_jengine_mask; /* last build: bit k set when class pair k ran the J-engine (builds
                             without K: Hermite densities of the pairs, no Cartesian block)     */
+    int y_kernel;        /* kernel of t_y_ms: 1 k_ygemm (512-row panels, when the reciprocal part
+                            runs without the short range beside it), 0 k_dgemm<2>            */
 } pbc_jk_counters;
 
 /* Creates a handle: validates and copies the inputs, builds the local pair
@@ -368,6 +371,43 @@ int pbc_jk_server_stats(pbc_jk_server *s, pbc_jk_server_counters *out);
 /* Cancels queued requests, waits for running builds, releases everything.
  * Tickets not yet waited for become invalid.  NULL is accepted. */
 void pbc_jk_server_destroy(pbc_jk_server *s);
+
+/* ---------------------------------------------------------------------
+ * Periodic Becke partition weights of atom-centred integration-grid points
+ * (Sec. 2.8, "Becke weights": eqs. becke_weight_definition,
+ * becke_vicinity_definition, becke_mu_definition, becke_switch_definition).
+ * For a point r whose origin atom is A, with X, Y running over the atom
+ * images within rcut of A's home position (the paper's radius is 17 bohr):
+ *   w(r) = P(A, r) / sum_X P(X, r),   P(X, r) = prod_{Y != X} s(X, Y, r),
+ *   s = (1 - f(f(f(u)))) / 2, f(x) = x (3 - x^2) / 2,
+ *   u = (|r - X| - |r - Y|) / |X - Y|.
+ * P(X, r) is zero once one switching factor is below delta; w is zero when
+ * P(A, r) is below delta.  The printed denominator's product over images is
+ * read as a sum over the atom images within the sphere.  The quadrature
+ * weight of a point (eq. total_weight_definition) is the caller's to apply.
+ */
+typedef struct pbc_becke pbc_becke; /* opaque plan: the image lists of a cell */
+
+/* Builds the plan for natom atoms at xyz (natom*3, bohr) in `cell`: for
+ * every atom, the list of atom images within rcut (> 0) of it, on the
+ * current device.  delta >= 0.  Inputs are copied. */
+int pbc_becke_create(const pbc_cell *cell, int natom, const double *xyz, double rcut, double delta,
+                     pbc_becke **out);
+
+/* Weights of npts points: d_pts (npts*3 doubles), d_origin (npts ints, the
+ * origin atom index of each point) and d_w (npts doubles, written) are device
+ * pointers; the kernel is queued on `stream` (a hipStream_t, NULL = default)
+ * and the call returns without waiting.  Points grouped by origin atom run
+ * fastest.  A point whose origin index is outside [0, natom) gets a NaN
+ * weight.  Calls on one plan may overlap (the plan is read only). */
+int pbc_becke_weights(pbc_becke *b, long npts, const double *d_pts, const int *d_origin, double *d_w,
+                      void *stream);
+
+/* Largest and total number of images in the plan's lists (NULL skips). */
+int pbc_becke_info(const pbc_becke *b, int *max_images, long *total_images);
+
+/* Frees the plan (NULL is accepted). */
+void pbc_becke_destroy(pbc_becke *b);
 
 /* Message of the last error on this thread ("" if none). */
 const char *pbc_jk_last_error(void);

@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "libpbcjk.so")
 OBJDIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["sr_slice_dp.hip", "sr_slice.hip", "sr_jk.hip", "sr_coop.hip", "sr_j.hip", "setup.cpp", "nbr.hip", "lr.hip",
-           "one_e.hip", "api.hip", "server.cpp"]
+           "one_e.hip", "becke.hip", "api.hip", "server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -56,6 +56,13 @@ int fail(int code, const std::string &msg)
     return code;
 }
 
+}  // namespace
+
+// Sets the thread's last-error message (other translation units of the library).
+int pbcjk::set_error(int code, const char *msg) { return fail(code, msg ? msg : ""); }
+
+namespace {
+
 #define HIPCHK(expr)                                                                            \
     do {                                                                                        \
         hipError_t e_ = (expr);                                                                 \
@@ -121,6 +128,12 @@ struct pbc_jk {
     hipGraphExec_t gexec = nullptr;
     double coop_ratio = kCoopRatio;
     int fp32_min_l = kFp32MinL;
+    bool chol_panel = true;        // blocked density factor (else one launch per column)
+    bool serial_lr = false;        // reciprocal part after the short range (else concurrently)
+    bool y_tall = true;            // low-rank products in 512-row panels (k_ygemm) when the reciprocal
+                                   // part runs alone, else k_dgemm<2>
+    bool y_always = false;         // k_ygemm beside the short range too
+    bool factor_first = true;      // density factor on the build stream before the short range
     int lr_rmax = 0;
     bool lr_ran = false;
     size_t nbr_bytes_needed = 0;   // set once the neighbour lists are counted
@@ -394,6 +407,11 @@ int create_device(pbc_jk *h)
     if (const char *e = std::getenv("PBCJK_Y_TILE")) h->y_tile = std::atoi(e) == 128 ? 128 : 64;
     if (const char *e = std::getenv("PBCJK_COOP_RATIO")) h->coop_ratio = std::max(0.0, std::atof(e));
     if (const char *e = std::getenv("PBCJK_FP32_MIN_L")) h->fp32_min_l = std::max(0, std::atoi(e));
+    if (const char *e = std::getenv("PBCJK_CHOL_PANEL")) h->chol_panel = std::atoi(e) != 0;
+    if (const char *e = std::getenv("PBCJK_SERIAL_LR")) h->serial_lr = std::atoi(e) != 0;
+    if (const char *e = std::getenv("PBCJK_YGEMM")) h->y_tall = std::atoi(e) != 0;
+    if (const char *e = std::getenv("PBCJK_YGEMM_ALWAYS")) h->y_always = std::atoi(e) != 0;
+    if (const char *e = std::getenv("PBCJK_FACTOR_FIRST")) h->factor_first = std::atoi(e) != 0;
     const int nG = (int)S.Gw.size();
     double budget_mb = h->lr_budget_mb > 0 ? h->lr_budget_mb : 16384.0;
     if (const char *e = std::getenv("PBCJK_LR_BUDGET_MB")) budget_mb = std::max(64.0, std::atof(e));
@@ -424,8 +442,12 @@ LatArgs lat_args(const Setup &S)
     return l;
 }
 
-// Real-space neighbour lists of every class pair: count, scan on the host,
-// fill in bra order.
+// Width of the distance buckets of the neighbour lists (bohr).
+constexpr double kNbrBucketWidth = 2.0;
+
+// Real-space neighbour lists of every class pair: count per (bra group,
+// distance bucket), scan on the host, fill in bra order, nearest buckets
+// first inside each bra group.
 int build_neighbours(pbc_jk *h)
 {
     const Setup &S = h->S;
@@ -433,8 +455,12 @@ int build_neighbours(pbc_jk *h)
     NbrArgs a{};
     a.pairs = h->d_pairs; a.groups = h->d_groups; a.lat = lat_args(S);
     a.w2 = S.omega * S.omega; a.d_ewald_R = S.d_ewald_R; a.rcap2 = S.r_cut > 0 ? S.r_cut * S.r_cut : 0.0;
+    double bw = kNbrBucketWidth;
+    if (const char *e = std::getenv("PBCJK_NBR_BW")) bw = std::atof(e);
+    a.inv_bw = bw > 0 ? 1.0 / bw : 0.0;
     int maxnb = 0;
     for (int c = 0; c < kNumClass; ++c) maxnb = std::max(maxnb, S.class_start[c + 1] - S.class_start[c]);
+    const long maxnc = (long)std::max(1, maxnb) * kNbrBuckets;
     int *d_counts = nullptr;
     long *d_offs = nullptr;
     int rc;
@@ -443,12 +469,13 @@ int build_neighbours(pbc_jk *h)
         void *a = nullptr, *b = nullptr;
         ~Tmp() { dfree(h, a); dfree(h, b); }
     } tmp{h};
-    if ((rc = dalloc(h, &d_counts, std::max(1, maxnb)))) return rc;
+    if ((rc = dalloc(h, &d_counts, maxnc))) return rc;
     tmp.a = d_counts;
-    if ((rc = dalloc(h, &d_offs, std::max(1, maxnb)))) return rc;
+    if ((rc = dalloc(h, &d_offs, maxnc))) return rc;
     tmp.b = d_offs;
-    std::vector<std::vector<long>> offs(21);
-    std::vector<int> cnt(std::max(1, maxnb));
+    // per class pair: the (bra group, bucket) counts, scanned when written
+    std::vector<std::vector<int>> cnts(21);
+    std::vector<long> offs(maxnc);
     long total = 0;
     int slot = 0;
     for (int cb = 0; cb < kNumClass; ++cb)
@@ -460,10 +487,11 @@ int build_neighbours(pbc_jk *h)
             if (a.nb == 0 || a.nk == 0) continue;
             a.mode = 0; a.counts = d_counts;
             HIPCHK(launch_nbr(a, st));
-            HIPCHK(hipMemcpyAsync(cnt.data(), d_counts, a.nb * sizeof(int), hipMemcpyDeviceToHost, st));
+            const long nc = (long)a.nb * kNbrBuckets;
+            cnts[slot].resize(nc);
+            HIPCHK(hipMemcpyAsync(cnts[slot].data(), d_counts, nc * sizeof(int), hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
-            offs[slot].resize(a.nb);
-            for (int i = 0; i < a.nb; ++i) { offs[slot][i] = total; total += cnt[i]; }
+            for (long i = 0; i < nc; ++i) total += cnts[slot][i];
         }
     h->nbr_off[21] = total;
     // the FP64/FP32 work lists exist only with mixed precision
@@ -489,7 +517,11 @@ int build_neighbours(pbc_jk *h)
             a.gk0 = S.class_start[ck]; a.nk = S.class_start[ck + 1] - S.class_start[ck];
             a.tri = (cb == ck);
             if (a.nb == 0 || a.nk == 0 || h->nbr_off[slot + 1] == h->nbr_off[slot]) continue;
-            HIPCHK(hipMemcpyAsync(d_offs, offs[slot].data(), a.nb * sizeof(long), hipMemcpyHostToDevice, st));
+            const long nc = (long)a.nb * kNbrBuckets;
+            long pos = h->nbr_off[slot];
+            for (long i = 0; i < nc; ++i) { offs[i] = pos; pos += cnts[slot][i]; }
+            std::vector<int>().swap(cnts[slot]);
+            HIPCHK(hipMemcpyAsync(d_offs, offs.data(), nc * sizeof(long), hipMemcpyHostToDevice, st));
             a.mode = 1; a.offsets = d_offs; a.out_bra = h->d_nbr_bra; a.out_ket = h->d_nbr_ket;
             HIPCHK(launch_nbr(a, st));
             HIPCHK(hipStreamSynchronize(st));
@@ -544,9 +576,60 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
             }
         }
 
-    // the reciprocal part and the self term go to the side stream
+    // B6 prelude: the density factor of the low-rank exchange, whose rank
+    // stays on the device.  By default it runs on the build stream before the
+    // short range (its column steps are short launches that the short-range
+    // kernels would hold back); the reciprocal products wait for it.
+    const int nG = (int)S.Gw.size();
+    const bool lr_on = (h->parts & PBC_JK_PART_LR) && nG > 0 && (wantJ || wantK);
+    const bool lowrank = lr_on && wantK && h->lr_mode == PBC_JK_LR_AUTO;
+    h->lr_ran = lowrank;
+    // Columns queued for the density factor: the rank of the last finished
+    // factor plus a margin when it is known without waiting, else the limit.
+    // A factor that needs more columns than queued does not converge and the
+    // dense form runs instead (decided on the device); the next build then
+    // queues the limit again.
+    int cap = h->lr_rmax;
+    if (lowrank && (h->capturing ? h->ctl_done : event_done(h->ev_ctl)) && h->h_ctl[2] && !h->h_ctl[1] &&
+        h->h_ctl[0] > 0)
+        cap = std::min(h->lr_rmax, ((h->h_ctl[0] + 64 + 63) / 64) * 64);
+    auto run_factor = [&](hipStream_t s) -> int {
+        // D~ = L L^T on the device; R = L L^T into T, then the entrywise check.
+        // The rank and the choice of form stay in the control block: every
+        // product below reads them there, so nothing waits on the host.
+        {
+            TimedLaunch tl(h, s, 4, 0.0);
+            HIPCHK(launch_pchol(h->d_Dt, n, h->lr_tol, cap, h->d_L, h->d_pw, h->d_pwi, h->d_ctl,
+                                h->chol_panel ? h->d_T : nullptr, s));
+        }
+        GemmArgs gr{};
+        gr.M = gr.N = n; gr.K = cap;
+        gr.A = h->d_L; gr.lda = n; gr.sA = 0; gr.transA = 1;
+        gr.B = h->d_L; gr.ldb = n; gr.sB = 0;
+        gr.C = h->d_T; gr.ldc = n; gr.sC = 0;
+        gr.nbatch = 1; gr.alpha0 = 1.0; gr.slices = 1;
+        gr.ctl = h->d_ctl; gr.ctl_mode = 2; gr.role = 1;
+        {
+            TimedLaunch tg(h, s, 2, 2.0 * (double)n * n);   // per unit of rank
+            HIPCHK(launch_dgemm(gr, s));
+        }
+        HIPCHK(launch_lowrank_check(h->d_Dt, h->d_T, n, h->d_pw, h->d_ctl, s));
+        // a copy of the decision for the next build's column count and for the counters
+        HIPCHK(hipMemcpyAsync(h->h_ctl, h->d_ctl, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+        if (!h->capturing) HIPCHK(hipEventRecord(h->ev_ctl, s));
+        return 0;
+    };
+
+    // the factor alone on the device (its column steps are single-workgroup
+    // launches that any concurrent kernel would hold back), then the
+    // reciprocal part and the self term on the side streams
     hipStream_t ls = h->side;
+    if (lowrank && h->factor_first) {
+        const int frc = run_factor(st);
+        if (frc) return frc;
+    }
     HIPCHK(hipEventRecord(h->ev_fork, st));
+    if (lr_on) HIPCHK(hipStreamWaitEvent(h->side2, h->ev_fork, 0));
     HIPCHK(hipStreamWaitEvent(ls, h->ev_fork, 0));
 
     // B3/B4: short-range J and K.  Per class pair: the density-weighted
@@ -642,11 +725,14 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
             }
     }
     if (!h->capturing) HIPCHK(hipEventRecord(h->ev[1], st));
+    if (h->serial_lr) {
+        // the reciprocal part after the short range instead of beside it
+        HIPCHK(hipEventRecord(h->ev_fork, st));
+        HIPCHK(hipStreamWaitEvent(ls, h->ev_fork, 0));
+    }
 
     // B6 prelude (side stream, beside the short range): the density factor of
     // the low-rank exchange, whose rank stays on the device.
-    const int nG = (int)S.Gw.size();
-    const bool lr_on = (h->parts & PBC_JK_PART_LR) && nG > 0 && (wantJ || wantK);
     if (!h->capturing) HIPCHK(hipEventRecord(h->ev[4], ls));
     SfacArgs sa{};
     sa.pairs = h->d_pairs; sa.sp_start = h->d_sp_start; sa.sp_pairs = h->d_sp_pairs;
@@ -676,47 +762,20 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
         return 0;
     };
     if (lr_on) {
-        HIPCHK(hipStreamWaitEvent(h->side2, h->ev_fork, 0));
         const int frc = sfac_j(0, std::min(h->gchunk, nG), h->side2);
         if (frc) return frc;
         HIPCHK(hipEventRecord(h->ev_sf, h->side2));
     }
-    const bool lowrank = lr_on && wantK && h->lr_mode == PBC_JK_LR_AUTO;
-    h->lr_ran = lowrank;
-    // Columns queued for the density factor: the rank of the last finished
-    // factor plus a margin when it is known without waiting, else the limit.
-    // A factor that needs more columns than queued does not converge and the
-    // dense form runs instead (decided on the device); the next build then
-    // queues the limit again.
-    int cap = h->lr_rmax;
-    if (lowrank && (h->capturing ? h->ctl_done : event_done(h->ev_ctl)) && h->h_ctl[2] && !h->h_ctl[1] &&
-        h->h_ctl[0] > 0)
-        cap = std::min(h->lr_rmax, ((h->h_ctl[0] + 64 + 63) / 64) * 64);
-    if (lowrank) {
-        // D~ = L L^T on the device; R = L L^T into T, then the entrywise check.
-        // The rank and the choice of form stay in the control block: every
-        // product below reads them there, so nothing waits on the host.
-        {
-            TimedLaunch tl(h, ls, 4, 0.0);
-            HIPCHK(launch_pchol(h->d_Dt, n, h->lr_tol, cap, h->d_L, h->d_pw, h->d_pwi, h->d_ctl, ls));
-        }
-        GemmArgs gr{};
-        gr.M = gr.N = n; gr.K = cap;
-        gr.A = h->d_L; gr.lda = n; gr.sA = 0; gr.transA = 1;
-        gr.B = h->d_L; gr.ldb = n; gr.sB = 0;
-        gr.C = h->d_T; gr.ldc = n; gr.sC = 0;
-        gr.nbatch = 1; gr.alpha0 = 1.0; gr.slices = 1;
-        gr.ctl = h->d_ctl; gr.ctl_mode = 2; gr.role = 1;
-        {
-            TimedLaunch tg(h, ls, 2, 2.0 * (double)n * n);   // per unit of rank
-            HIPCHK(launch_dgemm(gr, ls));
-        }
-        HIPCHK(launch_lowrank_check(h->d_Dt, h->d_T, n, h->d_pw, h->d_ctl, ls));
-        // a copy of the decision for the next build's column count and for the counters
-        HIPCHK(hipMemcpyAsync(h->h_ctl, h->d_ctl, 4 * sizeof(int), hipMemcpyDeviceToHost, ls));
-        if (!h->capturing) HIPCHK(hipEventRecord(h->ev_ctl, ls));
+    if (lowrank && !h->factor_first) {
+        const int frc = run_factor(ls);
+        if (frc) return frc;
     }
     h->lr_cap = cap;
+    // The 512-row panels of k_ygemm read each F_G once but hold a whole CU
+    // (148 KB of LDS); beside the short-range kernels the 64 x 64 tiles of
+    // k_dgemm<2> share the CUs better, so the panels run when the reciprocal
+    // part has the device to itself.
+    const bool ytall = h->y_tall && (h->y_always || h->serial_lr || !(h->parts & PBC_JK_PART_SR));
 
     // B5/B6: reciprocal-space J and K (side stream).  Both exchange forms
     // write the upper 128 x 128 tiles of K; with the low-rank form queued the
@@ -747,7 +806,8 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
                 g1.ctl = h->d_ctl; g1.ctl_mode = 4; g1.role = 2; g1.tile = h->y_tile;
                 {
                     TimedLaunch tl(h, ls, 30, 2.0 * nd * nd * nb);   // per unit of rank
-                    HIPCHK(launch_dgemm(g1, ls));
+                    HIPCHK(ytall ? launch_ygemm(g1, ls) : launch_dgemm(g1, ls));
+                    h->st.y_kernel = ytall ? 1 : 0;
                 }
                 // K += sum_b Y_b Y_b^T on the upper tiles, the batch split into
                 // slices (each slice's tile sums added atomically)

@@ -54,8 +54,9 @@ hipError_t launch_hdens(int cls, const HdensArgs &a, hipStream_t st);
 hipError_t launch_sr_j(int cb, int ck, const SRArgs &a, hipStream_t st);
 
 // Neighbour list of one class pair: every (bra group, ket group) that has at
-// least one real-space term for some density (mode 0 counts per bra, mode 1
-// writes the ket indices at the given per-bra offsets, in ket order).
+// least one real-space term for some density (mode 0 counts per bra and
+// distance bucket, mode 1 writes the ket indices at the given per-(bra,
+// bucket) offsets, in ket order inside a bucket).
 struct NbrArgs {
     const PairRec *pairs;
     const GroupRec *groups;
@@ -63,10 +64,16 @@ struct NbrArgs {
     LatArgs lat;
     double w2, d_ewald_R, rcap2;
     int mode;
-    int *counts;          // nb
-    const long *offsets;  // nb
+    double inv_bw;        // 1 / width (bohr) of the distance buckets; 0: one bucket
+    int *counts;          // nb * kNbrBuckets
+    const long *offsets;  // nb * kNbrBuckets
     int *out_bra, *out_ket;
 };
+// A bra group's entries are written in buckets of the distance between the two
+// group centres (nearest translate), nearest first: lanes of a wavefront then
+// hold ket groups at similar distances, whose quartets pass the real-space
+// sphere and the shift search alike.
+constexpr int kNbrBuckets = 16;
 hipError_t launch_nbr(const NbrArgs &a, hipStream_t st);
 
 // Per-build density screen of one class pair's neighbour list: entries with
@@ -181,21 +188,30 @@ struct GemmArgs {
                           // accumulate the upper tiles of K always use kGemmTile
 };
 hipError_t launch_dgemm(const GemmArgs &a, hipStream_t st);
+// C_b = alpha0 A B_b for the low-rank exchange factors (row-major A, B_b, C_b;
+// no transposes, no reduction), M gated by ctl_mode 4 as in launch_dgemm:
+// 64-column panels of up to 512 rows per workgroup (k_ygemm).
+hipError_t launch_ygemm(const GemmArgs &a, hipStream_t st);
+
+// Sets the thread's last-error message read by pbc_jk_last_error; returns code.
+int set_error(int code, const char *msg);
 // Edge of the upper blocks in which K is accumulated (and read back by the
 // final assembly), and the default GEMM output tile.
 constexpr int kGemmTile = 64;
 
 // Pivoted Cholesky of a symmetric n x n matrix D ~= L L^T, L stored by
-// columns (column j at L + j * n), one launch per column (steps after the
-// stop return at once), with the rank and the stop decision kept on the
-// device: nothing is read back to the host.  Stops when the largest
+// columns (column j at L + j * n), with the rank and the stop decision kept
+// on the device: nothing is read back to the host.  With a work matrix Aw
+// (n x n, overwritten) it runs in panels of 32 columns (one launch for the
+// panel's columns, one for the trailing update); without, one launch per
+// column.  Launches after the stop return at once.  Stops when the largest
 // remaining diagonal entry is <= tol * max diag(D) or after rmax columns.
 // ctl (4 ints): {rank, use_dense, done, -}.  work: n + 2 * ceil(n / 64) + 4
 // doubles and 2 * ceil(n / 64) ints (wi).  use_dense is set when the factor
 // did not converge within rmax columns or D has a diagonal entry below
 // -tol * max.
 hipError_t launch_pchol(const double *D, int n, double tol, int rmax, double *L, double *work, int *wi,
-                        int *ctl, hipStream_t st);
+                        int *ctl, double *Aw, hipStream_t st);
 // After R = L L^T: sets ctl[1] when max |D - R| exceeds 2 tol max diag(D)
 // plus the rounding allowance 4 n eps max diag(D).
 hipError_t launch_lowrank_check(const double *D, const double *R, int n, const double *work, int *ctl,

@@ -447,6 +447,117 @@ __global__ __launch_bounds__(256) void k_dgemm(GemmArgs g)
     }
 }
 
+// ---------------------------------------------------------------- Y_b^T = L^T F_b, tall tiles
+// The low-rank exchange products (C_b = A B_b with A the M x K factor rows,
+// M the rank read from the control block).  One workgroup of eight
+// wavefronts forms 64 columns of C_b for up to 512 rows, so that each F_b
+// column panel is read once per 512 rows of the factor (64 x 64 tiles read it
+// once per 64 rows).  The 16-row MFMA tiles are dealt to the wavefronts round
+// robin (wavefront w takes tiles w, w + 8, w + 16, w + 24): the two
+// wavefronts of a SIMD then carry about the same number.  K is staged in
+// slabs of 16 through two LDS buffers: the next slab is loaded into
+// registers while the current one is multiplied, and one barrier a slab
+// separates the buffers' reads from their next writes.
+constexpr int kYRows = 512, kYCols = 64, kYK = 16, kYThreads = 512;
+
+__global__ __launch_bounds__(kYThreads) void k_ygemm(GemmArgs g)
+{
+    __shared__ double As[2][kYK][kYRows + GPAD];
+    __shared__ double Bs[2][kYK][kYCols + GPAD];
+    int M = g.M;
+    if (g.ctl_mode) {
+        if (g.ctl[1]) return;
+        M = min(M, g.ctl[0]);
+    }
+    const int N = g.N, K = g.K;
+    // grid: (column tile, row chunk, batch) from the host's upper bounds
+    const int nx = (N + kYCols - 1) / kYCols, nch = (g.M + kYRows - 1) / kYRows;
+    const long vb = blockIdx.x;
+    const int tx = (int)(vb % nx), ch = (int)((vb / nx) % nch);
+    const int b = (int)(vb / ((long)nx * nch));
+    const int m0 = ch * kYRows, n0 = tx * kYCols;
+    if (m0 >= M || b >= g.nbatch) return;
+    const int rows = min(kYRows, M - m0);
+    const int mt = (rows + 15) / 16;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int my = mt > wave ? (mt - wave + 7) / 8 : 0;   // this wavefront's m-tiles (<= 4)
+    dbl4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+    const double *A = g.A;
+    const double *B = g.B + (long)b * g.sB;
+    // staging: thread t loads row m0 + t of the A slab (16 values along K)
+    // and two neighbouring values of row t / 32 of the B slab
+    double ra[kYK], rb[2];
+    const int bk = tid >> 5, bn = 2 * (tid & 31);
+    auto load = [&](int kt) {
+        const int k0 = kt * kYK;
+        if (tid < rows) {
+            const double *src = A + (long)(m0 + tid) * g.lda + k0;
+            if (k0 + kYK <= K) {
+#pragma unroll
+                for (int u = 0; u < kYK; ++u) ra[u] = src[u];
+            } else {
+#pragma unroll
+                for (int u = 0; u < kYK; ++u) ra[u] = k0 + u < K ? src[u] : 0.0;
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < kYK; ++u) ra[u] = 0.0;
+        }
+        const int gk = k0 + bk, gn = n0 + bn;
+        rb[0] = (gk < K && gn < N) ? B[(long)gk * g.ldb + gn] : 0.0;
+        rb[1] = (gk < K && gn + 1 < N) ? B[(long)gk * g.ldb + gn + 1] : 0.0;
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < kYK; ++u) As[buf][u][tid] = ra[u];
+        Bs[buf][bk][bn] = rb[0];
+        Bs[buf][bk][bn + 1] = rb[1];
+    };
+    const int nk = (K + kYK - 1) / kYK;
+    load(0);
+    stash(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) load(kt + 1);
+#pragma unroll
+        for (int kk = 0; kk < kYK; kk += 4) {
+            double bf[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bf[j] = Bs[cur][kk + lk][j * 16 + lr];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (i < my) {
+                    const double af = As[cur][kk + lk][(wave + 8 * i) * 16 + lr];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf[j], acc[i][j], 0, 0, 0);
+                }
+            }
+        }
+        if (kt + 1 < nk) stash(cur ^ 1);
+        __syncthreads();
+    }
+    double *C = g.C + (long)b * g.sC;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (i >= my) break;
+        const int rt = m0 + (wave + 8 * i) * 16;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gm = rt + lk + 4 * r, gn = n0 + j * 16 + lr;
+                if (gm < M && gn < N) C[(long)gm * g.ldc + gn] = g.alpha0 * acc[i][j][r];
+            }
+    }
+}
+
 // ---------------------------------------------------------------- pivoted Cholesky
 // Step k: every block reduces the per-block maxima of the remaining diagonal
 // left by step k - 1 to the pivot p, then forms rows [64 b, 64 b + 64) of
@@ -502,10 +613,15 @@ __global__ __launch_bounds__(1024) void k_pchol_init(const double *D, int n, dou
     }
 }
 
-__global__ __launch_bounds__(256) void k_pchol_step(const double *D, int n, int k, double *L, double *work, int *wi,
-                                                   int *ctl)
+// One workgroup of four wavefronts per 64 rows: the dot products over the
+// previous columns are split over the wavefronts, four independent loads in
+// flight each, so that a step waits on about k / 16 L2 round trips.
+constexpr int kCholWaves = 4;
+
+__global__ __launch_bounds__(64 * kCholWaves) void k_pchol_step(const double *D, int n, int k, double *L,
+                                                               double *work, int *wi, int *ctl)
 {
-    __shared__ double sred[4][kCholRows];
+    __shared__ double sred[kCholWaves][kCholRows];
     __shared__ double s_piv;
     __shared__ int s_p, s_done;
     if (threadIdx.x == 0) s_done = ctl[2];
@@ -533,15 +649,27 @@ __global__ __launch_bounds__(256) void k_pchol_step(const double *D, int n, int 
         return;
     }
     const int i = blockIdx.x * kCholRows + l;
-    double s = 0.0;
-    if (i < n)
-        for (int j = w; j < k; j += 4) s += L[(long)j * n + i] * L[(long)j * n + p];
-    sred[w][l] = s;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    if (i < n) {
+        constexpr int W = kCholWaves;
+        int j = w;
+        for (; j + 3 * W < k; j += 4 * W) {
+            s0 += L[(long)j * n + i] * L[(long)j * n + p];
+            s1 += L[(long)(j + W) * n + i] * L[(long)(j + W) * n + p];
+            s2 += L[(long)(j + 2 * W) * n + i] * L[(long)(j + 2 * W) * n + p];
+            s3 += L[(long)(j + 3 * W) * n + i] * L[(long)(j + 3 * W) * n + p];
+        }
+        for (; j < k; j += W) s0 += L[(long)j * n + i] * L[(long)j * n + p];
+    }
+    sred[w][l] = (s0 + s1) + (s2 + s3);
     __syncthreads();
     if (w == 0) {
         double v = -1e300;
         if (i < n) {
-            const double x = (D[(long)p * n + i] - (sred[0][l] + sred[1][l] + sred[2][l] + sred[3][l])) / sqrt(piv);
+            double s = 0.0;
+#pragma unroll
+            for (int u = 0; u < kCholWaves; ++u) s += sred[u][l];
+            const double x = (D[(long)p * n + i] - s) / sqrt(piv);
             L[(long)k * n + i] = x;
             const double d = (i == p) ? 0.0 : diag[i] - x * x;
             diag[i] = d;
@@ -551,6 +679,160 @@ __global__ __launch_bounds__(256) void k_pchol_step(const double *D, int n, int 
         for (int off = 32; off > 0; off >>= 1) argmax_merge(v, ii, __shfl_xor(v, off, 64), __shfl_xor(ii, off, 64));
         if (l == 0) { pv_out[blockIdx.x] = v; pi_out[blockIdx.x] = ii; }
     }
+}
+
+// Blocked form (right-looking): panels of kCholPanel columns.  One workgroup
+// takes the panel's columns one after the other from the trailing matrix A
+// (D minus the outer products of all earlier panels): pivot p = the largest
+// remaining diagonal entry, L_ki = (A_pi - sum over the panel's earlier
+// columns j of L_ji L_jp) / sqrt(d_p), d_i -= L_ki^2.  Each thread owns rows
+// tid + 512 q and keeps, in registers, their remaining diagonal and their
+// values in the panel's columns; the pivot row's values reach the other
+// threads through LDS from the thread that owns it, so a step reads only the
+// pivot row of A from memory.  Then k_pchol_update subtracts the panel's
+// outer products from the trailing matrix.  Same columns as the
+// one-launch-per-column steps, up to the order of the sums.
+constexpr int kCholPanel = 16;
+constexpr int kCholPanelThreads = 512;
+constexpr int kCholPanelRows = 4;      // rows per thread
+// Larger matrices take the per-column steps: there the trailing updates (a
+// pass over the n x n matrix per panel) cost more than the launches saved.
+constexpr int kCholPanelMaxN = kCholPanelRows * kCholPanelThreads;
+
+__global__ __launch_bounds__(kCholPanelThreads) void k_pchol_panel(const double *A, int n, int k0, int kend,
+                                                                  double *L, double *work, int *ctl)
+{
+    constexpr int T = kCholPanelThreads, NW = T / 64, R = kCholPanelRows, P = kCholPanel;
+    __shared__ double s_v[NW];
+    __shared__ int s_i[NW];
+    __shared__ double s_lp[P];
+    __shared__ double s_piv;
+    __shared__ int s_p, s_done;
+    if (threadIdx.x == 0) s_done = ctl[2];
+    __syncthreads();
+    if (s_done) return;
+    const int nblk = (n + kCholRows - 1) / kCholRows;
+    double *diag = work;
+    const double stop = work[n + 2 * nblk];
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    double d[R], pl[R][P];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int i = tid + q * T;
+        d[q] = i < n ? diag[i] : -1e300;
+#pragma unroll
+        for (int t = 0; t < P; ++t) pl[q][t] = 0.0;
+    }
+    int k = k0;
+    bool stopped = false;
+    for (; k < kend; ++k) {
+        double bv = -1e300;
+        int bi = 0x7fffffff;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int i = tid + q * T;
+            if (i < n) argmax_merge(bv, bi, d[q], i);
+        }
+        for (int off = 32; off > 0; off >>= 1) argmax_merge(bv, bi, __shfl_xor(bv, off, 64), __shfl_xor(bi, off, 64));
+        if (l == 0) { s_v[w] = bv; s_i[w] = bi; }
+        __syncthreads();
+        if (tid == 0) {
+            double t = s_v[0];
+            int ti = s_i[0];
+            for (int u = 1; u < NW; ++u) argmax_merge(t, ti, s_v[u], s_i[u]);
+            s_piv = t;
+            s_p = ti;
+        }
+        __syncthreads();
+        const double piv = s_piv;
+        const int p = s_p;
+        if (!(piv > stop)) {
+            stopped = true;
+            break;
+        }
+        const int kk = k - k0;
+        // the pivot row's panel values (zero beyond column kk) from its owner
+        if (tid == p % T) {
+            const int qp = p / T;
+#pragma unroll
+            for (int q = 0; q < R; ++q)
+                if (q == qp)
+#pragma unroll
+                    for (int t = 0; t < P; ++t) s_lp[t] = pl[q][t];
+        }
+        __syncthreads();
+        const double inv = 1.0 / sqrt(piv);
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int i = tid + q * T;
+            if (i < n) {
+                double v0 = A[(long)p * n + i], v1 = 0.0;
+#pragma unroll
+                for (int t = 0; t < P; t += 2) {
+                    v0 -= pl[q][t] * s_lp[t];
+                    v1 -= pl[q][t + 1] * s_lp[t + 1];
+                }
+                const double x = (v0 + v1) * inv;
+                L[(long)k * n + i] = x;
+#pragma unroll
+                for (int t = 0; t < P; ++t)
+                    if (t == kk) pl[q][t] = x;
+                d[q] = (i == p) ? 0.0 : d[q] - x * x;
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int i = tid + q * T;
+        if (i < n) diag[i] = d[q];
+    }
+    if (stopped && tid == 0) {
+        ctl[0] = k;
+        ctl[2] = 1;
+    }
+}
+
+// dst = src - sum_{k0 <= j < k0 + kb} L_j L_j^T (full matrix, 64 x 64 tiles,
+// 4 x 4 outputs a thread); nothing once the factor has stopped.
+__global__ __launch_bounds__(256) void k_pchol_update(const double *src, double *dst, int n, int k0, int kb,
+                                                     const double *L, const int *ctl)
+{
+    __shared__ double Li[kCholPanel][64], Lj[kCholPanel][64];
+    if (ctl[2]) return;
+    const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+    const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+    for (int e = tid; e < kb * 64; e += 256) {
+        const int t = e >> 6, c = e & 63;
+        Li[t][c] = i0 + c < n ? L[(long)(k0 + t) * n + i0 + c] : 0.0;
+        Lj[t][c] = j0 + c < n ? L[(long)(k0 + t) * n + j0 + c] : 0.0;
+    }
+    __syncthreads();
+    double acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int i = i0 + ty * 4 + a, j = j0 + tx * 4 + b;
+            acc[a][b] = (i < n && j < n) ? src[(long)i * n + j] : 0.0;
+        }
+    for (int t = 0; t < kb; ++t) {
+        double x[4], y[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) x[a] = Li[t][ty * 4 + a];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) y[b] = Lj[t][tx * 4 + b];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] -= x[a] * y[b];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int i = i0 + ty * 4 + a, j = j0 + tx * 4 + b;
+            if (i < n && j < n) dst[(long)i * n + j] = acc[a][b];
+        }
 }
 
 // After the last step: rank = rmax when the factor did not stop by itself;
@@ -686,7 +968,7 @@ __global__ __launch_bounds__(256) void k_lowrank_check(const double *D, const do
 }  // namespace
 
 hipError_t launch_pchol(const double *D, int n, double tol, int rmax, double *L, double *work, int *wi,
-                        int *ctl, hipStream_t st)
+                        int *ctl, double *Aw, hipStream_t st)
 {
     const int nblk = (n + kCholRows - 1) / kCholRows;
     if (n <= kCholSingleMax) {
@@ -694,10 +976,24 @@ hipError_t launch_pchol(const double *D, int n, double tol, int rmax, double *L,
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_pchol_init, dim3(1), dim3(1024), 0, st, D, n, tol, work, wi, ctl);
+    if (Aw && n <= kCholPanelMaxN) {
+        // panels: the trailing matrix lives in Aw (D itself for the first panel)
+        const int nt = (n + 63) / 64;
+        for (int k0 = 0; k0 < rmax; k0 += kCholPanel) {
+            const int kb = std::min(kCholPanel, rmax - k0);
+            hipLaunchKernelGGL(k_pchol_panel, dim3(1), dim3(kCholPanelThreads), 0, st, k0 == 0 ? D : (const double *)Aw,
+                               n, k0, k0 + kb, L, work, ctl);
+            if (k0 + kb < rmax)
+                hipLaunchKernelGGL(k_pchol_update, dim3(nt, nt), dim3(256), 0, st, k0 == 0 ? D : (const double *)Aw, Aw,
+                                   n, k0, kb, (const double *)L, (const int *)ctl);
+        }
+        hipLaunchKernelGGL(k_pchol_fin, dim3(1), dim3(256), 0, st, n, rmax, (const double *)work, (const int *)wi, ctl);
+        return hipGetLastError();
+    }
     // every column up to rmax is queued; the steps after the stop return at
     // their first instruction (the caller keeps rmax near the expected rank)
     for (int k = 0; k < rmax; ++k)
-        hipLaunchKernelGGL(k_pchol_step, dim3(nblk), dim3(256), 0, st, D, n, k, L, work, wi, ctl);
+        hipLaunchKernelGGL(k_pchol_step, dim3(nblk), dim3(64 * kCholWaves), 0, st, D, n, k, L, work, wi, ctl);
     hipLaunchKernelGGL(k_pchol_fin, dim3(1), dim3(256), 0, st, n, rmax, (const double *)work, (const int *)wi, ctl);
     return hipGetLastError();
 }
@@ -772,6 +1068,16 @@ hipError_t launch_dgemm_t(const GemmArgs &a, hipStream_t st)
         case 3: hipLaunchKernelGGL((k_dgemm<3, T>), grid, dim3(256), 0, st, a); break;
         default: hipLaunchKernelGGL((k_dgemm<0, T>), grid, dim3(256), 0, st, a); break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_ygemm(const GemmArgs &a, hipStream_t st)
+{
+    if (a.M <= 0 || a.N <= 0 || a.K <= 0 || a.nbatch <= 0) return hipSuccess;
+    if (a.transA || a.transB || a.reduce || a.upper || a.alpha || (a.ctl_mode != 0 && a.ctl_mode != 4))
+        return hipErrorInvalidValue;
+    const long blocks = (long)((a.N + kYCols - 1) / kYCols) * ((a.M + kYRows - 1) / kYRows) * a.nbatch;
+    hipLaunchKernelGGL(k_ygemm, dim3((unsigned)blocks), dim3(kYThreads), 0, st, a);
     return hipGetLastError();
 }
 

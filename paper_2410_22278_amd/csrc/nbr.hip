@@ -47,6 +47,19 @@ __device__ bool group_pair_has_term(const NbrArgs &a, const GroupRec &gb, const 
     return false;
 }
 
+// Distance bucket of a group pair: |C_b - C_k - R| for the rounded translate R.
+__device__ __forceinline__ int nbr_bucket(const NbrArgs &a, const GroupRec &gb, const GroupRec &gk)
+{
+    const double x[3] = {gb.C[0] - gk.C[0], gb.C[1] - gk.C[1], gb.C[2] - gk.C[2]};
+    double n[3], L[3];
+    nearest_translate(a.lat, x, n);
+    lat_image(a.lat, x, n[0], n[1], n[2], L);
+    const double t = sqrt(L[0] * L[0] + L[1] * L[1] + L[2] * L[2]) * a.inv_bw;
+    return t < (double)(kNbrBuckets - 1) ? (int)t : kNbrBuckets - 1;
+}
+
+// One wavefront per bra group.  Lane b < kNbrBuckets keeps bucket b's count
+// (mode 0) or its next write position (mode 1).
 __global__ __launch_bounds__(256) void k_nbr(NbrArgs a)
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -54,25 +67,32 @@ __global__ __launch_bounds__(256) void k_nbr(NbrArgs a)
     if (bi >= a.nb) return;
     const GroupRec gb = a.groups[a.gb0 + bi];
     const int jlo = a.tri ? bi : 0;
-    long base = a.mode ? a.offsets[bi] : 0;
-    int cnt = 0;
+    long mine = (a.mode && lane < kNbrBuckets) ? a.offsets[(long)bi * kNbrBuckets + lane] : 0;
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int j0 = jlo; j0 < a.nk; j0 += 64) {
         const int j = j0 + lane;
         bool keep = false;
+        int bk = 0;
         if (j < a.nk) {
             const GroupRec gk = a.groups[a.gk0 + j];
             keep = group_pair_test(a, gb, gk) && group_pair_has_term(a, gb, gk);
+            if (keep) bk = nbr_bucket(a, gb, gk);
         }
-        const unsigned long long m = __ballot(keep);
-        if (a.mode && keep) {
-            const long pos = base + cnt + __popcll(m & below);
-            a.out_bra[pos] = bi;
-            a.out_ket[pos] = j;
+        if (__ballot(keep) == 0) continue;
+        for (int b = 0; b < kNbrBuckets; ++b) {
+            const unsigned long long m = __ballot(keep && bk == b);
+            if (m == 0) continue;
+            // read with every lane active: lane b need not be among the writers
+            const long start = __shfl(mine, b, 64);
+            if (a.mode && keep && bk == b) {
+                const long pos = start + __popcll(m & below);
+                a.out_bra[pos] = bi;
+                a.out_ket[pos] = j;
+            }
+            if (lane == b) mine += __popcll(m);
         }
-        cnt += __popcll(m);
     }
-    if (!a.mode && lane == 0) a.counts[bi] = cnt;
+    if (!a.mode && lane < kNbrBuckets) a.counts[(long)bi * kNbrBuckets + lane] = (int)mine;
 }
 
 // Screen flags of one entry: bit 0 keep in FP64, bit 1 keep in FP32.

@@ -89,12 +89,10 @@ __device__ __forceinline__ void add_term(const EAxis<LA, LB, EV> &Ex, const EAxi
         }
 }
 
-// Adds the density contractions of one contracted block (components
-// IC0 .. IC0+NIC-1 of the first ket shell) into the J and K halves (hardware
-// FP64 atomics); blocks of several slices add up to the full contraction.
+// The bra-block part of J: jab[ia][ib] = 2 w sum_cd acc[ia][ib][c][d] D_cd.
 template <int LA, int LB, int LC, int LD, int IC0, int NIC>
-__device__ __forceinline__ void scatter_block(const SRArgs &a, const double (&acc)[ncart(LA)][ncart(LB)][NIC][ncart(LD)],
-                                              double w, int aoA, int aoB, int aoC, int aoD)
+__device__ __forceinline__ void contract_ab(const SRArgs &a, const double (&acc)[ncart(LA)][ncart(LB)][NIC][ncart(LD)],
+                                            double w, int aoC, int aoD, double (&jab)[ncart(LA)][ncart(LB)])
 {
     constexpr int NA = ncart(LA), NB = ncart(LB), ND = ncart(LD);
     const double *Dt = a.Dt;
@@ -109,8 +107,22 @@ __device__ __forceinline__ void scatter_block(const SRArgs &a, const double (&ac
             for (int ic = 0; ic < NIC; ++ic)
 #pragma unroll
                 for (int id = 0; id < ND; ++id) s += acc[ia][ib][ic][id] * Dt[(aoC + ic) * n + aoD + id];
-            atomicAdd(&a.X[(aoA + ia) * n + aoB + ib], 2.0 * w * s);
+            jab[ia][ib] = 2.0 * w * s;
         }
+}
+
+// Adds the density contractions of one contracted block (components
+// IC0 .. IC0+NIC-1 of the first ket shell) into the J and K halves (hardware
+// FP64 atomics), except the bra block of J (contract_ab), which the caller
+// adds; blocks of several slices add up to the full contraction.
+template <int LA, int LB, int LC, int LD, int IC0, int NIC>
+__device__ __forceinline__ void scatter_block(const SRArgs &a, const double (&acc)[ncart(LA)][ncart(LB)][NIC][ncart(LD)],
+                                              double w, int aoA, int aoB, int aoC, int aoD)
+{
+    constexpr int NA = ncart(LA), NB = ncart(LB), ND = ncart(LD);
+    const double *Dt = a.Dt;
+    const int n = a.nbfc;
+    aoC += IC0;
 #pragma unroll
     for (int ic = 0; ic < NIC; ++ic)
 #pragma unroll
@@ -324,12 +336,25 @@ void k_sr_jk(SRArgs a)
     const int ns = a.nshell;
     unsigned long long cnt_q = 0, cnt_t = 0;
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool have = e < (long)*a.count;
+    const int bi = have ? a.nbr_bra[e] : -1;
+    // all lanes hold one bra group (the usual case: the lists run in bra order)
+    const int bi0 = __builtin_amdgcn_readfirstlane(bi);
+    const bool uni = __builtin_amdgcn_ballot_w64(have && bi != bi0) == 0;
+    double jab[NA][NB];
+#pragma unroll
+    for (int i0 = 0; i0 < NA; ++i0)
+#pragma unroll
+        for (int i1 = 0; i1 < NB; ++i1) jab[i0][i1] = 0.0;
+    int aoA = 0, aoB = 0;
 
-    if (e < (long)*a.count) {
-        const int bi = a.nbr_bra[e], j = a.nbr_ket[e];
+    if (have) {
+        const int j = a.nbr_ket[e];
         const GroupRec gb = a.groups[a.gb0 + bi];
         const GroupRec gk = a.groups[a.gk0 + j];
         const int A = gb.shA, B = gb.shB, C = gk.shA, D = gk.shB;
+        aoA = gb.aoA;
+        aoB = gb.aoB;
         double wD = a.Dmax[A * ns + B];
         wD = fmax(wD, a.Dmax[C * ns + D]);
         wD = fmax(wD, a.Dmax[A * ns + C]);
@@ -358,9 +383,9 @@ void k_sr_jk(SRArgs a)
         // Ket pairs outer (each lane reads its own ket records once), bra pairs
         // inner.  A group's pairs are stored by descending Q, so the first pair
         // that fails the Cauchy-Schwarz test ends its loop.  When every lane of
-        // the wavefront has the same bra group (the usual case: the lists run
-        // in bra order), the bra records are read through the constant address
-        // space, so their loads are scalar and the bra loop is uniform.
+        // the wavefront has the same bra group, the bra records are read
+        // through the constant address space, so their loads are scalar and the
+        // bra loop is uniform.
         auto run = [&](auto bpairs, int pbs, int pbe) {
             const int pk_end = (gb.Qmax * gk.Qmax * wD > a.d_schwarz) ? gk.pend : gk.pstart;
             for (int pk = gk.pstart; pk < pk_end; ++pk) {
@@ -370,8 +395,7 @@ void k_sr_jk(SRArgs a)
                                                             cnt_t, ent_terms);
             }
         };
-        const int bi0 = __builtin_amdgcn_readfirstlane(bi);
-        if (__builtin_amdgcn_ballot_w64(bi != bi0) == 0) {
+        if (uni) {
             const CPairPtr cp = (CPairPtr)a.pairs;
             run(cp, __builtin_amdgcn_readfirstlane(gb.pstart), __builtin_amdgcn_readfirstlane(gb.pend));
         } else {
@@ -379,7 +403,30 @@ void k_sr_jk(SRArgs a)
         }
         if (ent_terms > 0) {
             const double w = (a.tri && j == bi) ? 0.5 : 1.0;
+            contract_ab<LA, LB, LC, LD, IC0, NIC>(a, acc, w, gk.aoA, gk.aoB, jab);
             scatter_block<LA, LB, LC, LD, IC0, NIC>(a, acc, w, gb.aoA, gb.aoB, gk.aoA, gk.aoB);
+        }
+    }
+    // The bra block of J: with one bra group in the wavefront, summed across
+    // the lanes before one atomic per element; otherwise per lane.
+    {
+        const int n = a.nbfc;
+        if (uni) {
+            const int ra = __builtin_amdgcn_readfirstlane(aoA), rb = __builtin_amdgcn_readfirstlane(aoB);
+#pragma unroll
+            for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+                for (int ib = 0; ib < NB; ++ib) {
+                    double v = jab[ia][ib];
+                    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+                    if (lane == 0 && v != 0.0) atomicAdd(&a.X[(ra + ia) * n + rb + ib], v);
+                }
+        } else if (have) {
+#pragma unroll
+            for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+                for (int ib = 0; ib < NB; ++ib)
+                    if (jab[ia][ib] != 0.0) atomicAdd(&a.X[(aoA + ia) * n + aoB + ib], jab[ia][ib]);
         }
     }
     // per-lane counters, summed across the wave before one atomic each

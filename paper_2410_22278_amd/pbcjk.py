@@ -64,7 +64,7 @@ class pbc_jk_counters(ctypes.Structure):
                 ("n_group_pairs", c_double), ("lr_rank", c_double), ("t_chol_ms", c_double),
                 ("gemm_kernel", c_int), ("t_sr_class_ms", c_double * 21), ("t_y_ms", c_double),
                 ("y_flops", c_double), ("n_y", c_int), ("sr_fold_mask", c_int),
-                ("sr_kernel_mask", c_int), ("sr_jengine_mask", c_int)]
+                ("sr_kernel_mask", c_int), ("sr_jengine_mask", c_int), ("y_kernel", c_int)]
 
 
 class pbc_jk_server_config(ctypes.Structure):
@@ -147,6 +147,15 @@ def load():
     lib.pbc_jk_server_destroy.restype = None
     lib.pbc_jk_last_error.argtypes = []
     lib.pbc_jk_last_error.restype = c_char_p
+    lib.pbc_becke_create.argtypes = [POINTER(pbc_cell), c_int, POINTER(c_double), c_double, c_double,
+                                     POINTER(c_void_p)]
+    lib.pbc_becke_create.restype = c_int
+    lib.pbc_becke_weights.argtypes = [c_void_p, ctypes.c_long, c_void_p, c_void_p, c_void_p, c_void_p]
+    lib.pbc_becke_weights.restype = c_int
+    lib.pbc_becke_info.argtypes = [c_void_p, POINTER(c_int), POINTER(ctypes.c_long)]
+    lib.pbc_becke_info.restype = c_int
+    lib.pbc_becke_destroy.argtypes = [c_void_p]
+    lib.pbc_becke_destroy.restype = None
     _lib = lib
     return lib
 
@@ -435,6 +444,66 @@ class Server:
             load().pbc_jk_server_destroy(c_void_p(self.s))
             self.s = None
             self._live.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Becke:
+    """The library's periodic Becke-weight plan (pbc_becke_*) for one cell:
+    weights(pts, origin) on torch cuda tensors (float64 N x 3, int32 N)."""
+
+    def __init__(self, cell, xyz, rcut: float = 17.0, delta: float = 1e-14):
+        lib = load()
+        c = pbc_cell()
+        c.a[:] = [float(v) for v in np.asarray(cell, float).ravel()]
+        x = np.ascontiguousarray(np.asarray(xyz, float).reshape(-1, 3))
+        self.natom = len(x)
+        out = c_void_p()
+        _check(lib.pbc_becke_create(byref(c), self.natom, x.ctypes.data_as(POINTER(c_double)), float(rcut),
+                                    float(delta), byref(out)))
+        self.b = out.value
+
+    def info(self):
+        m, t = c_int(), ctypes.c_long()
+        _check(load().pbc_becke_info(c_void_p(self.b), byref(m), byref(t)))
+        return {"max_images": m.value, "total_images": t.value}
+
+    def weights(self, pts, origin, out=None, stream=None):
+        """Queues the weights of the points on `stream` (default: torch's
+        current stream) and returns the output tensor (not synchronised)."""
+        import torch
+        if pts.dtype != torch.float64 or not pts.is_cuda or not pts.is_contiguous() or pts.dim() != 2 \
+                or pts.shape[1] != 3:
+            raise ValueError("pts must be a contiguous float64 cuda tensor of shape (N, 3)")
+        if origin.dtype != torch.int32 or not origin.is_cuda or not origin.is_contiguous() \
+                or origin.shape != (pts.shape[0],):
+            raise ValueError("origin must be a contiguous int32 cuda tensor of shape (N,)")
+        n = pts.shape[0]
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device=pts.device)
+        elif out.dtype != torch.float64 or not out.is_cuda or not out.is_contiguous() or out.shape != (n,):
+            raise ValueError("out must be a contiguous float64 cuda tensor of shape (N,)")
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        _check(load().pbc_becke_weights(c_void_p(self.b), n, c_void_p(pts.data_ptr()),
+                                        c_void_p(origin.data_ptr()), c_void_p(out.data_ptr()),
+                                        c_void_p(stream.cuda_stream)))
+        return out
+
+    def close(self):
+        if getattr(self, "b", None):
+            load().pbc_becke_destroy(c_void_p(self.b))
+            self.b = None
 
     def __enter__(self):
         return self
