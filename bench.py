@@ -366,10 +366,12 @@ def kernel_candidates(acc, steps):
     return cands
 
 
-def roof(c):
+def roof(c, workload):
+    """The roofline object of one kernel; `traffic` only for the workload whose
+    counters profiles/traffic.json holds (the 64-water cell, FP64 or mixed)."""
     ach = c["flops_per_build"] / (c["ms_per_build"] * 1e-3) / 1e12 if c["ms_per_build"] > 0 else 0.0
     return {"kernel": c["kernel"], "bound": c["bound"], "achieved": ach, "peak": c["peak"], "unit": "TFLOP/s",
-            "frac": ach / c["peak"], "traffic": traffic_for(c["name"]),
+            "frac": ach / c["peak"], "traffic": traffic_for(c["name"]) if workload in ("cfg2", "cfg3") else None,
             "launches_per_build": c["launches_per_build"],
             "avg_launch_ms": c["ms_per_build"] / max(1e-9, c["launches_per_build"]),
             "ms_per_build": c["ms_per_build"], "flops_per_build": c["flops_per_build"]}
@@ -489,8 +491,9 @@ def main():
                         parts=parts)
     steps = args.steps
     cands = kernel_candidates(acc, steps)
-    roof_main = roof(cands[0])
-    roof2 = roof(next((c for c in cands[1:] if c["bound"] != cands[0]["bound"]), cands[min(1, len(cands) - 1)]))
+    roof_main = roof(cands[0], name)
+    roof2 = roof(next((c for c in cands[1:] if c["bound"] != cands[0]["bound"]), cands[min(1, len(cands) - 1)]),
+                 name)
     st = acc["st"]
     lat = np.array(acc["lat"])
     ms = acc["ms_per_step"]
@@ -583,9 +586,9 @@ def main():
                              "setup_s": a4["setup_s"],
                              "stage_ms_per_build": a4["stage"], "terms_per_build": a4["st"]["terms"],
                              "terms_fp32_fraction": a4["st"]["terms_fp32"] / max(1.0, a4["st"]["terms"]),
-                             "roofline": roof(c4[0]),
+                             "roofline": roof(c4[0], cname),
                              "roofline_secondary": roof(next((c for c in c4[1:] if c["bound"] != c4[0]["bound"]),
-                                                            c4[min(1, len(c4) - 1)])),
+                                                            c4[min(1, len(c4) - 1)]), cname),
                              "sr_all_classes": sr_summary(a4, 1, c4),
                              "vs_oracle": errors_vs_golden(cname, s4, a4, np)}
                 del a4
