@@ -227,6 +227,9 @@ def oracle_counts(name):
         return None
 
 
+BECKE_FLOPS_PER_FACTOR = 35.0
+
+
 def time_becke(steps, np, torch, inputs, pbcjk, cpu_sample=True):
     """Periodic Becke weights (the paper's Sec. 2.8 grid partition) of
     atom-centred product grids on the diamond cell's 512 atoms: 20 radial x
@@ -251,11 +254,20 @@ def time_becke(steps, np, torch, inputs, pbcjk, cpu_sample=True):
         ms = e0.elapsed_time(e1) / steps
         w = dw.cpu().numpy()
         info = b.info()
+        evals = b.evaluations()
     V = abs(float(np.linalg.det(s4.cell)))
     out = {"workload": "Becke weights: diamond cell (512 atoms, a = 41.05 bohr), 20 x 8 x 16 product grid per atom "
                        "(1,310,720 points), 17 bohr sphere, delta 1e-14",
            "steps": steps, "ms_per_launch": ms, "points_per_s": len(pts) / (ms * 1e-3),
-           "images_per_atom": info["max_images"], "sum_w_over_V": float((wq * w).sum()) / V}
+           "images_per_atom": info["max_images"], "sum_w_over_V": float((wq * w).sum()) / V,
+           "switching_factors_per_launch": evals}
+    # FP64 VALU roofline: ~35 FLOP per switching factor (|X - Y|^2, an rsqrt with two
+    # Newton steps, u, the three-fold polynomial, the product)
+    ach = evals * BECKE_FLOPS_PER_FACTOR / (ms * 1e-3) / 1e12
+    out["roofline"] = {"kernel": "k_becke: periodic Becke weights, one lane per grid point", "bound": "alu",
+                       "achieved": ach, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                       "frac": ach / FP64_VALU_PEAK_TFLOPS, "traffic": None, "launches_per_build": 1.0,
+                       "avg_launch_ms": ms, "flops_per_launch": evals * BECKE_FLOPS_PER_FACTOR}
     if cpu_sample:
         from oracle import becke as obk
         sel = np.sort(np.random.default_rng(7).choice(len(pts), 512, replace=False))
@@ -481,7 +493,8 @@ def main():
         print(json.dumps({"metric": "Becke weights points/s", "value": r["points_per_s"], "unit": "points/s",
                           "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": r["ms_per_launch"],
                           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-                          "data": "synthetic", "config": {"workload": r["workload"]}, "detail": r}), flush=True)
+                          "data": "synthetic", "config": {"workload": r["workload"]}, "roofline": r["roofline"],
+                          "cpu_baseline": r.get("cpu_baseline"), "detail": r}), flush=True)
         return
     name = "cfg2" if args.workload == "headline" else args.workload
     system = inputs.CONFIGS[name]()

@@ -406,6 +406,11 @@ int pbc_becke_weights(pbc_becke *b, long npts, const double *d_pts, const int *d
 /* Largest and total number of images in the plan's lists (NULL skips). */
 int pbc_becke_info(const pbc_becke *b, int *max_images, long *total_images);
 
+/* Switching factors s(X, Y, r) evaluated by the plan's last pbc_becke_weights
+ * call (the work the kernel did: at most M (M - 1) a point for M images, fewer
+ * where a factor fell below delta).  Waits for that call's stream. */
+int pbc_becke_evaluations(pbc_becke *b, double *evaluations);
+
 /* Frees the plan (NULL is accepted). */
 void pbc_becke_destroy(pbc_becke *b);
 

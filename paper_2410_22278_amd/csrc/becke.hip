@@ -36,6 +36,8 @@ struct pbc_becke {
     double delta = 0.0;
     double *d_img = nullptr;   // total_images records of 4 doubles (x, y, z, 0)
     int *d_off = nullptr;      // natom + 1 offsets into d_img (in records)
+    unsigned long long *d_evals = nullptr;   // switching factors evaluated by the last call
+    void *last_stream = nullptr;
 };
 
 namespace pbcjk {
@@ -55,7 +57,7 @@ __device__ __forceinline__ double becke_switch(double u)
 }
 
 template <class IP>
-__device__ __forceinline__ double becke_point(IP img, int M, const double r[3], double delta)
+__device__ __forceinline__ double becke_point(IP img, int M, const double r[3], double delta, unsigned &evals)
 {
     constexpr int NB = kBeckeBlock;
     double num = 0.0, den = 0.0;
@@ -86,6 +88,7 @@ __device__ __forceinline__ double becke_point(IP img, int M, const double r[3], 
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
                 if (live[j] && x0 + j != y) {
+                    ++evals;
                     const double p = X[j][0] - Y0, q = X[j][1] - Y1, t = X[j][2] - Y2;
                     const double u = (dX[j] - dY) * fast_rsqrt(p * p + q * q + t * t);
                     const double s = becke_switch(u);
@@ -118,6 +121,7 @@ struct BeckeArgs {
     long npts;
     double delta;
     double *w;
+    unsigned long long *evals;   // + switching factors evaluated (summed per wavefront)
 };
 
 __global__ __launch_bounds__(256) void k_becke(BeckeArgs a)
@@ -129,21 +133,27 @@ __global__ __launch_bounds__(256) void k_becke(BeckeArgs a)
     if (bad) A = -1;
     const int A0 = __builtin_amdgcn_readfirstlane(A);
     const bool uni = __builtin_amdgcn_ballot_w64(have && A != A0) == 0;
-    if (!have) return;
-    if (A < 0) {
-        a.w[g] = __builtin_nan("");   // origin index out of range
-        return;
+    unsigned evals = 0;
+    if (have) {
+        if (A < 0) {
+            a.w[g] = __builtin_nan("");   // origin index out of range
+        } else {
+            const double r[3] = {a.pts[3 * g], a.pts[3 * g + 1], a.pts[3 * g + 2]};
+            const int i0 = a.off[A], M = a.off[A + 1] - i0;
+            double w;
+            if (uni) {
+                const CDblPtr cp = (CDblPtr)a.img + 4L * __builtin_amdgcn_readfirstlane(i0);
+                w = becke_point(cp, __builtin_amdgcn_readfirstlane(M), r, a.delta, evals);
+            } else {
+                w = becke_point(a.img + 4L * i0, M, r, a.delta, evals);
+            }
+            a.w[g] = w;
+        }
     }
-    const double r[3] = {a.pts[3 * g], a.pts[3 * g + 1], a.pts[3 * g + 2]};
-    const int i0 = a.off[A], M = a.off[A + 1] - i0;
-    double w;
-    if (uni) {
-        const CDblPtr cp = (CDblPtr)a.img + 4L * __builtin_amdgcn_readfirstlane(i0);
-        w = becke_point(cp, __builtin_amdgcn_readfirstlane(M), r, a.delta);
-    } else {
-        w = becke_point(a.img + 4L * i0, M, r, a.delta);
-    }
-    a.w[g] = w;
+    // every lane of the wavefront is active again here
+    unsigned long long e = evals;
+    for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
+    if ((threadIdx.x & 63) == 0 && e) atomicAdd(a.evals, e);
 }
 
 int becke_fail(int code, const char *msg) { return set_error(code, msg); }
@@ -235,11 +245,14 @@ extern "C" int pbc_becke_create(const pbc_cell *cell, int natom, const double *x
     hipError_t e = hipGetDevice(&b->device);
     if (e == hipSuccess) e = hipMalloc((void **)&b->d_img, img.size() * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void **)&b->d_off, off.size() * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_evals, sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMemcpy(b->d_img, img.data(), img.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(b->d_off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(b->d_evals, 0, sizeof(unsigned long long));
     if (e != hipSuccess) {
         (void)hipFree(b->d_img);
         (void)hipFree(b->d_off);
+        (void)hipFree(b->d_evals);
         delete b;
         return becke_fail(e == hipErrorOutOfMemory ? PBC_JK_ENOMEM : PBC_JK_EDEVICE, hipGetErrorString(e));
     }
@@ -255,11 +268,15 @@ extern "C" int pbc_becke_weights(pbc_becke *b, long npts, const double *d_pts, c
     if (npts == 0) return PBC_JK_OK;
     if (!d_pts || !d_origin || !d_w) return becke_fail(PBC_JK_EINVAL, "pbc_becke_weights: NULL array");
     BECKE_HIP(hipSetDevice(b->device));
-    BeckeArgs a{b->d_img, b->d_off, b->natom, d_pts, d_origin, npts, b->delta, d_w};
+    BeckeArgs a{b->d_img, b->d_off, b->natom, d_pts, d_origin, npts, b->delta, d_w, b->d_evals};
     const long blocks = (npts + 255) / 256;
     if (blocks > 0x7fffffffL) return becke_fail(PBC_JK_EINVAL, "pbc_becke_weights: too many points");
+    // the counter is cleared by a kernel on the same stream (a memset node would
+    // not replay reliably inside a captured graph)
+    BECKE_HIP(launch_fill((double *)b->d_evals, 1, 0.0, (hipStream_t)stream));
     hipLaunchKernelGGL(k_becke, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, a);
     BECKE_HIP(hipGetLastError());
+    b->last_stream = stream;
     return PBC_JK_OK;
 }
 
@@ -271,11 +288,23 @@ extern "C" int pbc_becke_info(const pbc_becke *b, int *max_images, long *total_i
     return PBC_JK_OK;
 }
 
+extern "C" int pbc_becke_evaluations(pbc_becke *b, double *evaluations)
+{
+    if (!b || !evaluations) return becke_fail(PBC_JK_EINVAL, "pbc_becke_evaluations: NULL argument");
+    BECKE_HIP(hipSetDevice(b->device));
+    BECKE_HIP(hipStreamSynchronize((hipStream_t)b->last_stream));
+    unsigned long long e = 0;
+    BECKE_HIP(hipMemcpy(&e, b->d_evals, sizeof e, hipMemcpyDeviceToHost));
+    *evaluations = (double)e;
+    return PBC_JK_OK;
+}
+
 extern "C" void pbc_becke_destroy(pbc_becke *b)
 {
     if (!b) return;
     (void)hipSetDevice(b->device);
     (void)hipFree(b->d_img);
     (void)hipFree(b->d_off);
+    (void)hipFree(b->d_evals);
     delete b;
 }

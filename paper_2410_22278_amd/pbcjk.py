@@ -154,6 +154,8 @@ def load():
     lib.pbc_becke_weights.restype = c_int
     lib.pbc_becke_info.argtypes = [c_void_p, POINTER(c_int), POINTER(ctypes.c_long)]
     lib.pbc_becke_info.restype = c_int
+    lib.pbc_becke_evaluations.argtypes = [c_void_p, POINTER(c_double)]
+    lib.pbc_becke_evaluations.restype = c_int
     lib.pbc_becke_destroy.argtypes = [c_void_p]
     lib.pbc_becke_destroy.restype = None
     _lib = lib
@@ -477,6 +479,12 @@ class Becke:
         m, t = c_int(), ctypes.c_long()
         _check(load().pbc_becke_info(c_void_p(self.b), byref(m), byref(t)))
         return {"max_images": m.value, "total_images": t.value}
+
+    def evaluations(self) -> float:
+        """Switching factors evaluated by the last weights() call (waits for it)."""
+        e = c_double()
+        _check(load().pbc_becke_evaluations(c_void_p(self.b), byref(e)))
+        return e.value
 
     def weights(self, pts, origin, out=None, stream=None):
         """Queues the weights of the points on `stream` (default: torch's

@@ -37,7 +37,9 @@ def _gpu_weights(lib, cell, xyz, pts, origin, **kw):
         do = torch.from_numpy(np.ascontiguousarray(origin, dtype=np.int32)).cuda()
         w = b.weights(dp, do)
         torch.cuda.synchronize()
-        return w.cpu().numpy(), b.info()
+        info = b.info()
+        info["evaluations"] = b.evaluations()
+        return w.cpu().numpy(), info
 
 
 def _cell3():
@@ -57,6 +59,9 @@ def test_grid_parity_and_integral(lib, oracle_mod):
           f"sum w/V gpu {float((wq * w).sum()) / abs(np.linalg.det(cell)):.6f}", flush=True)
     assert d < TOL
     assert abs(float((wq * w).sum()) - float((wq * ref).sum())) < 1e-9 * abs(np.linalg.det(cell))
+    # work counter: at least one factor a point, at most M (M - 1) a point
+    M = info["max_images"]
+    assert len(pts) <= info["evaluations"] <= len(pts) * M * (M - 1)
 
 
 def test_shuffled_and_ragged(lib, oracle_mod):
