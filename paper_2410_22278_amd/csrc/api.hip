@@ -778,7 +778,7 @@ int run_build_streams(pbc_jk *h, const double *dD, double *dJ, double *dK, doubl
     const bool ytall = h->y_tall && (h->y_always || h->serial_lr || !(h->parts & PBC_JK_PART_SR));
 
     // B5/B6: reciprocal-space J and K (side stream).  Both exchange forms
-    // write the upper 128 x 128 tiles of K; with the low-rank form queued the
+    // write the upper 64 x 64 tiles of K; with the low-rank form queued the
     // dense products are gated on its failure (and the other way round).
     if (lr_on) {
         const int ntile = (n + kGemmTile - 1) / kGemmTile, upper_tiles = ntile * (ntile + 1) / 2;
